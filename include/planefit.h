@@ -1,0 +1,142 @@
+/*
+ * planefit: dense per-pixel plane fitting to depth images on AMD Instinct
+ * MI355X (gfx950), after Papadakis & Willis, "Real-Time Surface Fitting to
+ * RGBD Sensor Data" (2017).
+ *
+ * What is computed (Sec. II).  Each pixel (x, y) of a depth image Z with a
+ * pinhole camera (fx, fy, cx, cy) has the ray tangents
+ *     u = tan(theta_x) = (x - cx)/fx,   v = tan(theta_y) = (y - cy)/fy   (Eq. 10)
+ * and the back-projected point P = Z (u, v, 1) (Eq. 1, Eq. 11).  Dividing the
+ * plane equation aX + bY + cZ + d = 0 by Z gives a u + b v + c + d/Z = 0
+ * (Eq. 12): the coefficients (a, b, c) multiply camera-only quantities and d
+ * multiplies the disparity w = 1/Z.  For every pixel the library fits a plane
+ * to the k x k window centred on it:
+ *
+ *   PF_IMPLICIT  minimises sum_i (a u_i + b v_i + c + d w_i)^2 with
+ *                |(a, b, c)| = 1 (Sec. II-A, scatter matrix of Eq. 14).
+ *   PF_EXPLICIT  minimises sum_i (a u_i + b v_i + c - w_i)^2 (Sec. II-B,
+ *                Eq. 15-16); the plane is a X + b Y + c Z - 1 = 0.
+ *
+ * The camera-only window moments (sum u^2, sum u v, sum u, sum v^2, sum v,
+ * N) are fixed once the calibration and k are known (Sec. II-A/B); per frame
+ * only window sums of w, u w, v w, w^2 and a validity count are needed, and
+ * they are taken from integral images (Sec. II-C) built on the GPU.
+ *
+ * Outputs per pixel, for the plane n . P + d = 0 with |n| = 1 and d >= 0
+ * (the normal faces the camera):
+ *   normals   [3][H][W] float32, channel-planar (n_x plane, n_y plane, n_z plane)
+ *   offsets   [H][W]    float32, d in the depth unit
+ *   residuals [H][W]    float32, RMS over the window of (n . P_i + d) / Z_i
+ *                       (point-to-plane distance over depth: dimensionless)
+ *   status    [H][W]    uint8 (optional): bit 0 = invalid window,
+ *                       bit 1 = ill-conditioned normal (implicit mode,
+ *                       kappa = l3/(l2 - l1) above pf_params.kappa_flag).
+ * A pixel is valid iff its mask byte (if a mask is given) is non-zero and its
+ * depth is finite and > 0.  A window is valid iff all k*k pixels lie inside
+ * the image and are valid; invalid windows get NaN outputs and status bit 0.
+ * That is a result, not an error.  Results are specified for depths in
+ * [1e-3, 1e3] (any unit, consistently used).
+ *
+ * Memory: every image pointer given to pf_fit_planes is a DEVICE pointer owned
+ * by the caller; images are row-major with a pitch in elements.  Calls are
+ * enqueue-only on the given HIP stream and return before the GPU finishes;
+ * the caller keeps the buffers alive until the stream passes this point.
+ * No function aborts or throws; errors come back as pf_status codes.
+ */
+#ifndef PLANEFIT_H
+#define PLANEFIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PF_OK = 0,
+  PF_ERR_NULL = 1,        /* a required pointer is NULL */
+  PF_ERR_SHAPE = 2,       /* H or W < 1, H or W > 65535, or H*W > 2^31 */
+  PF_ERR_WINDOW = 3,      /* k not odd, k < 3, k > 63, or k > min(H, W) */
+  PF_ERR_INTRINSICS = 4,  /* fx, fy not finite and > 0, or cx, cy not finite */
+  PF_ERR_PITCH = 5,       /* a pitch is smaller than W */
+  PF_ERR_ALIGNMENT = 6,   /* a float pointer is not 4-byte aligned */
+  PF_ERR_WORKSPACE = 7,   /* workspace missing or smaller than required */
+  PF_ERR_UNSUPPORTED = 8, /* mode / precision / flag value not supported */
+  PF_ERR_HIP = 9          /* the HIP runtime reported an error (pf_last_hip_error) */
+} pf_status;
+
+/* Pinhole intrinsics in pixels (Eq. 1 with the lens correction delta = 0). */
+typedef struct {
+  double fx, fy, cx, cy;
+} pf_intrinsics;
+
+enum { PF_IMPLICIT = 0, PF_EXPLICIT = 1 };
+
+/* Arithmetic of the window moments and the per-pixel solve.
+ *  PF_PREC_FP64: disparity integrands, integral-image sums and the solve in
+ *                FP64 (MI355X runs FP64 vector FMA at the FP32 rate); the
+ *                accurate default.
+ *  PF_PREC_FP32: everything in FP32; the throughput reference.  Integral-image
+ *                differences lose digits to cancellation, so its errors are
+ *                reported, not held to the FP64 oracle's tolerances. */
+enum { PF_PREC_FP64 = 0, PF_PREC_FP32 = 1 };
+
+typedef struct {
+  int32_t window;     /* k: odd, 3 <= k <= 63, k <= min(H, W) */
+  int32_t mode;       /* PF_IMPLICIT or PF_EXPLICIT */
+  int32_t precision;  /* PF_PREC_FP64 or PF_PREC_FP32 */
+  int32_t flags;      /* reserved, must be 0 */
+  double kappa_flag;  /* implicit mode: set status bit 1 where kappa > this; 0 = never */
+} pf_params;
+
+typedef struct pf_plan pf_plan;
+
+/* Host only.  Validates the camera, frame size and parameters, precomputes the
+ * camera-only window moments for (camera, k) (Sec. II-A/B) and the launch
+ * geometry.  Allocates host memory only (no device memory).  The plan is
+ * immutable; it may be shared by threads and streams.  *out is set to NULL on
+ * error. */
+pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t width,
+                         const pf_params* params, pf_plan** out);
+
+/* Accepts NULL. */
+void pf_plan_destroy(pf_plan* plan);
+
+/* Bytes of device workspace pf_fit_planes needs with this plan (0 for the
+ * fused path, which keeps its integral images on chip). */
+size_t pf_plan_workspace_bytes(const pf_plan* plan);
+
+/* Camera-only moments of the window centred at pixel (x0, y0), in the paper's
+ * uncentred form: out = [sum u^2, sum u v, sum u, sum v^2, sum v, N] (the
+ * upper-left 3x3 block of Eq. 14, equal to the matrix of Eq. 16).  Host only;
+ * evaluated from the plan's closed form, no summation.  Returns PF_ERR_NULL
+ * for NULL arguments. */
+pf_status pf_plan_camera_moments(const pf_plan* plan, int64_t x0, int64_t y0, double out[6]);
+
+/* Enqueue the per-pixel fits of one frame on `stream` (a hipStream_t; NULL =
+ * the default stream).
+ *   depth      device float[H][depth_pitch], depth per pixel (0 / NaN = no data)
+ *   mask       device uint8[H][mask_pitch] or NULL; 0 marks a pixel invalid
+ *   normals    device float[3][H][W]
+ *   offsets    device float[H][W]
+ *   residuals  device float[H][W]
+ *   status     device uint8[H][W] or NULL
+ *   workspace  device buffer of at least pf_plan_workspace_bytes() (may be
+ *              NULL when that is 0)
+ * Argument checks run on the host before anything is enqueued. */
+pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_pitch,
+                        const uint8_t* mask, int64_t mask_pitch, float* normals,
+                        float* offsets, float* residuals, uint8_t* status, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
+/* Static description of a status code. */
+const char* pf_status_string(pf_status s);
+
+/* The hipError_t behind the most recent PF_ERR_HIP on this thread (0 if none). */
+int pf_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

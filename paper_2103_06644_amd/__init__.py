@@ -1,0 +1,16 @@
+"""planefit for MI355X: per-pixel RGBD plane fitting with HIP kernels.
+
+After Papadakis & Willis, "Real-Time Surface Fitting to RGBD Sensor Data":
+each pixel's k x k window is fitted with a plane in tan(theta)/disparity
+space (Eq. 12), from integral-image window sums (Sec. II-C) and closed-form
+camera-only moments.  The library is libplanefit.so (C ABI in
+include/planefit.h); this package is its Python binding.
+"""
+from ._binding import (  # noqa: F401
+    EXPORTS, MODES, PRECISIONS, STATUS_ILL_CONDITIONED, STATUS_INVALID, Plan,
+    PlanefitArgumentError, PlanefitError, fit_planes, get_plan, load_library, status_string,
+)
+
+__all__ = ["fit_planes", "Plan", "get_plan", "load_library", "status_string",
+           "PlanefitError", "PlanefitArgumentError", "MODES", "PRECISIONS",
+           "STATUS_INVALID", "STATUS_ILL_CONDITIONED", "EXPORTS"]

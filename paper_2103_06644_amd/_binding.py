@@ -1,0 +1,230 @@
+"""ctypes binding of libplanefit.so (argument marshalling only).
+
+Every step of the fit runs in the HIP kernels of the library; this module only
+checks tensor shapes and devices, allocates the outputs through torch and
+passes raw device pointers and the current HIP stream across the C ABI
+declared in include/planefit.h.  If the library is missing the calls raise:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libplanefit.so")
+
+PF_OK = 0
+STATUS_NAMES = {0: "PF_OK", 1: "PF_ERR_NULL", 2: "PF_ERR_SHAPE", 3: "PF_ERR_WINDOW",
+                4: "PF_ERR_INTRINSICS", 5: "PF_ERR_PITCH", 6: "PF_ERR_ALIGNMENT",
+                7: "PF_ERR_WORKSPACE", 8: "PF_ERR_UNSUPPORTED", 9: "PF_ERR_HIP"}
+MODES = {"implicit": 0, "explicit": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+
+# status byte bits written per pixel
+STATUS_INVALID = 1
+STATUS_ILL_CONDITIONED = 2
+
+
+class PlanefitError(RuntimeError):
+    """A pf_* call failed; .code holds the pf_status value."""
+
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class PlanefitArgumentError(PlanefitError, ValueError):
+    pass
+
+
+class _Intrinsics(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_double), ("fy", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("kappa_flag", ctypes.c_double)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+EXPORTS = ("pf_plan_create", "pf_plan_destroy", "pf_plan_workspace_bytes",
+           "pf_plan_camera_moments", "pf_fit_planes", "pf_status_string",
+           "pf_last_hip_error")
+
+
+def load_library(path: str | None = None):
+    """Load libplanefit.so (built by paper_2103_06644_amd.build); raises if absent."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None and path is None:
+            return _lib
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise RuntimeError(f"planefit HIP library not built: {p} is missing "
+                               "(run `python -m paper_2103_06644_amd.build`)")
+        lib = ctypes.CDLL(p)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        lib.pf_plan_create.argtypes = [ctypes.POINTER(_Intrinsics), i64, i64,
+                                       ctypes.POINTER(_Params), ctypes.POINTER(vp)]
+        lib.pf_plan_create.restype = i32
+        lib.pf_plan_destroy.argtypes = [vp]
+        lib.pf_plan_destroy.restype = None
+        lib.pf_plan_workspace_bytes.argtypes = [vp]
+        lib.pf_plan_workspace_bytes.restype = ctypes.c_size_t
+        lib.pf_plan_camera_moments.argtypes = [vp, i64, i64, ctypes.POINTER(ctypes.c_double)]
+        lib.pf_plan_camera_moments.restype = i32
+        lib.pf_fit_planes.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp,
+                                      ctypes.c_size_t, vp]
+        lib.pf_fit_planes.restype = i32
+        lib.pf_status_string.argtypes = [i32]
+        lib.pf_status_string.restype = ctypes.c_char_p
+        lib.pf_last_hip_error.argtypes = []
+        lib.pf_last_hip_error.restype = ctypes.c_int
+        if path is None:
+            _lib = lib
+        return lib
+
+
+def status_string(code: int) -> str:
+    return load_library().pf_status_string(int(code)).decode()
+
+
+def _check(code: int):
+    if code == PF_OK:
+        return
+    lib = load_library()
+    msg = lib.pf_status_string(code).decode()
+    if code == 9:
+        raise PlanefitError(code, f"{msg} (hipError_t {lib.pf_last_hip_error()})")
+    raise PlanefitArgumentError(code, msg)
+
+
+class Plan:
+    """A pf_plan: camera + frame size + window + mode + precision (host-only object)."""
+
+    def __init__(self, intrinsics, height: int, width: int, window: int,
+                 mode: str = "implicit", precision: str = "fp64", kappa_flag: float = 0.0,
+                 flags: int = 0):
+        lib = load_library()
+        fx, fy, cx, cy = (float(v) for v in intrinsics)
+        if mode not in MODES:
+            raise ValueError(f"mode must be one of {sorted(MODES)}")
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        self._intr = _Intrinsics(fx, fy, cx, cy)
+        self._params = _Params(int(window), MODES[mode], PRECISIONS[precision], int(flags),
+                               float(kappa_flag))
+        h = ctypes.c_void_p()
+        _check(lib.pf_plan_create(ctypes.byref(self._intr), int(height), int(width),
+                                  ctypes.byref(self._params), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+        self.intrinsics = (fx, fy, cx, cy)
+        self.height, self.width, self.window = int(height), int(width), int(window)
+        self.mode, self.precision, self.kappa_flag = mode, precision, float(kappa_flag)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self._lib.pf_plan_workspace_bytes(self._h))
+
+    def camera_moments(self, x0: int, y0: int):
+        out = (ctypes.c_double * 6)()
+        _check(self._lib.pf_plan_camera_moments(self._h, int(x0), int(y0), out))
+        return list(out)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.pf_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_plan_cache: dict = {}
+_plan_cache_lock = threading.Lock()
+
+
+def get_plan(intrinsics, height, width, window, mode="implicit", precision="fp64",
+             kappa_flag=0.0) -> Plan:
+    key = (tuple(float(v) for v in intrinsics), int(height), int(width), int(window), mode,
+           precision, float(kappa_flag))
+    with _plan_cache_lock:
+        p = _plan_cache.get(key)
+        if p is None:
+            p = Plan(intrinsics, height, width, window, mode, precision, kappa_flag)
+            _plan_cache[key] = p
+        return p
+
+
+def _stream_handle(torch, device, stream):
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "implicit",
+               precision: str = "fp64", kappa_flag: float = 0.0, out=None, stream=None):
+    """Per-pixel plane fits of a depth frame on the GPU.
+
+    depth       float32 tensor [H, W] on a HIP device (unit stride along W)
+    intrinsics  (fx, fy, cx, cy) in pixels
+    window      odd window size k
+    valid_mask  optional uint8/bool tensor [H, W] on the same device (0 = invalid)
+    out         optional (normals [3,H,W], offsets [H,W], residuals [H,W], status [H,W])
+    Returns (normals, offsets, residuals, status), enqueued on the current stream.
+    """
+    import torch
+    if depth.dim() != 2 or depth.dtype != torch.float32 or depth.device.type != "cuda":
+        raise ValueError("depth must be a float32 [H, W] tensor on a HIP device")
+    if depth.stride(1) != 1:
+        raise ValueError("depth must have unit stride along W")
+    H, W = depth.shape
+    plan = get_plan(intrinsics, H, W, window, mode, precision, kappa_flag)
+    dev = depth.device
+    mptr, mpitch = None, 0
+    if valid_mask is not None:
+        if valid_mask.shape != depth.shape or valid_mask.device != dev:
+            raise ValueError("valid_mask must match depth's shape and device")
+        if valid_mask.dtype == torch.bool:
+            valid_mask = valid_mask.view(torch.uint8)
+        if valid_mask.dtype != torch.uint8 or valid_mask.stride(1) != 1:
+            raise ValueError("valid_mask must be uint8/bool with unit stride along W")
+        mptr, mpitch = valid_mask.data_ptr(), valid_mask.stride(0)
+    if out is None:
+        normals = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+        offsets = torch.empty((H, W), dtype=torch.float32, device=dev)
+        residuals = torch.empty((H, W), dtype=torch.float32, device=dev)
+        status = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    else:
+        normals, offsets, residuals, status = out
+        for t, shp, dt in ((normals, (3, H, W), torch.float32), (offsets, (H, W), torch.float32),
+                           (residuals, (H, W), torch.float32), (status, (H, W), torch.uint8)):
+            if tuple(t.shape) != shp or t.dtype != dt or not t.is_contiguous() or t.device != dev:
+                raise ValueError("out tensors must be contiguous, on depth's device, with "
+                                 "shapes [3,H,W], [H,W], [H,W], [H,W]")
+    ws = plan.workspace_bytes
+    work = torch.empty(ws, dtype=torch.uint8, device=dev) if ws else None
+    with torch.cuda.device(dev):
+        code = plan._lib.pf_fit_planes(
+            plan.handle, ctypes.c_void_p(depth.data_ptr()), depth.stride(0),
+            ctypes.c_void_p(mptr) if mptr else None, mpitch,
+            ctypes.c_void_p(normals.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+            ctypes.c_void_p(residuals.data_ptr()), ctypes.c_void_p(status.data_ptr()),
+            ctypes.c_void_p(work.data_ptr()) if work is not None else None, ws,
+            _stream_handle(torch, dev, stream))
+    _check(code)
+    return normals, offsets, residuals, status

@@ -1,0 +1,604 @@
+// planefit: per-pixel RGBD plane fits on MI355X (gfx950).  C-ABI in
+// include/planefit.h.
+//
+// One fused kernel runs the whole per-frame path of the paper's integral-image
+// method (Sec. II-A..C) for a tile of output pixels:
+//
+//   integrands  w = 1/Z and its products with the window coordinates, shifted
+//               by a per-tile reference disparity so the sums stay small;
+//   2D scan     a transposed integral-image sweep: every thread owns one image
+//               column and carries its running column sums down the tile (the
+//               vertical prefix), then every thread owns a run of P output
+//               pixels of a row and carries running row sums of the column
+//               sums (the horizontal prefix).  Each prefix runs as two cursors
+//               k samples apart that add exactly the same values in exactly
+//               the same order, so "lead - lag" is bit-for-bit the difference
+//               of two integral-image entries k apart.  That is the box sum of
+//               Sec. II-C with no k-row history kept anywhere;
+//   box sums    lead minus lag, in both directions: the four-corner rule;
+//   solve       explicit (Eq. 15-16) in closed form, or implicit (Eq. 14) as a
+//               3x3 symmetric eigenproblem after eliminating d;
+//   store       normals (channel-planar), offsets, residuals, status.
+//
+// Only depth comes in and only the five outputs go out: the integral images
+// live in registers and LDS.  The camera-only moments (sum u^2 ... N) enter in
+// closed form in window-centred coordinates, where the k x k window has
+// sum x' = sum y' = sum x'y' = 0 and sum x'^2 = sum y'^2 = k^2 (k^2 - 1)/12.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "planefit.h"
+
+namespace {
+
+constexpr int kBlock = 256;   // threads per workgroup; also the strip width in input columns
+constexpr int kRows = 8;      // output rows per vertical/horizontal round
+constexpr int kRuns = 32;     // runs per row in the horizontal phase
+constexpr int kRunLen = 8;    // output pixels per run (kRuns * kRunLen >= kBlock)
+constexpr int kPitch = kBlock + kBlock / 8 + 1;  // LDS row pitch after padding
+constexpr int kMaxWindow = 63;
+
+__host__ __device__ inline int lds_index(int i) { return i + (i >> 3); }
+
+struct FitArgs {
+  const float* depth;
+  const uint8_t* mask;
+  float* normals;
+  float* offsets;
+  float* residuals;
+  uint8_t* status;
+  int64_t depth_pitch;
+  int64_t mask_pitch;
+  int64_t plane;  // H * W
+  int H, W, k, r;
+  int tile_w;     // output columns per strip
+  int tile_h;     // output rows per band
+  int n_strips;
+  int n_bands;
+  double fx, fy, cx, cy;
+  double inv_fx, inv_fy;
+  double S2, inv_S2, N, inv_N;
+  double kappa_flag;
+};
+
+// ---------------------------------------------------------------------------
+// Per-pixel integrand (Sec. II-A: the entries of Eq. 14 that depend on depth).
+// ---------------------------------------------------------------------------
+__device__ inline bool depth_valid(float z) {
+  // finite and strictly positive; written on the bit pattern so no fast-math
+  // assumption can drop the test
+  const uint32_t b = __float_as_uint(z);
+  return ((b & 0x7f800000u) != 0x7f800000u) && z > 0.0f;
+}
+
+template <typename T>
+struct Cursor {
+  T w, yw, ww;  // sums of (w - w_ref), (y - y_ref)(w - w_ref), (w - w_ref)^2
+  int n;        // number of valid pixels
+  __device__ void clear() {
+    w = yw = ww = T(0);
+    n = 0;
+  }
+};
+
+template <typename T>
+__device__ inline void add_pixel(const FitArgs& a, int x, int y, T w_ref, int y_ref,
+                                 Cursor<T>& c) {
+  if (x < 0 || x >= a.W || y < 0 || y >= a.H) return;
+  const float z = a.depth[(int64_t)y * a.depth_pitch + x];
+  bool ok = depth_valid(z);
+  if (a.mask) ok = ok && a.mask[(int64_t)y * a.mask_pitch + x] != 0;
+  if (!ok) return;
+  const T wh = T(1) / T(z) - w_ref;
+  c.w += wh;
+  c.yw += T(y - y_ref) * wh;
+  c.ww += wh * wh;
+  c.n += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric 3x3 smallest eigenpair.
+//
+// Eigenvalues in closed form from the characteristic polynomial by the
+// trigonometric solution of the cubic (O. K. Smith, "Eigenvalues of a
+// symmetric 3x3 matrix", CACM 4(4), 1961) in FP32; for FP64 the smallest one
+// is then refined by Newton's method on det(B - l I) in FP64.  The
+// eigenvector is the best-conditioned cross product of two rows of B - l1 I
+// (as in J. Kopp, "Efficient numerical diagonalization of hermitian 3x3
+// matrices", 2008).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Eig3 {
+  T l1, l2, l3;  // ascending
+  T n[3];        // unit eigenvector of l1
+  bool degenerate;
+};
+
+template <typename T>
+__device__ inline T det3(T a00, T a01, T a02, T a11, T a12, T a22) {
+  return a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02) +
+         a02 * (a01 * a12 - a11 * a02);
+}
+
+template <typename T>
+__device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22) {
+  Eig3<T> e;
+  e.degenerate = false;
+  T s = fmax(fabs(c00), fmax(fabs(c11), fabs(c22)));
+  if (!(s > T(0)) || !isfinite(s)) {
+    e.l1 = e.l2 = e.l3 = T(0);
+    e.n[0] = T(0); e.n[1] = T(0); e.n[2] = T(-1);
+    e.degenerate = true;
+    return e;
+  }
+  const T is = T(1) / s;
+  const T b00 = c00 * is, b01 = c01 * is, b02 = c02 * is;
+  const T b11 = c11 * is, b12 = c12 * is, b22 = c22 * is;
+
+  // closed-form estimates in FP32
+  const float q = float(b00 + b11 + b22) * (1.0f / 3.0f);
+  const float d0 = float(b00) - q, d1 = float(b11) - q, d2 = float(b22) - q;
+  const float f01 = float(b01), f02 = float(b02), f12 = float(b12);
+  const float p2 = d0 * d0 + d1 * d1 + d2 * d2 + 2.0f * (f01 * f01 + f02 * f02 + f12 * f12);
+  const float p = sqrtf(p2 * (1.0f / 6.0f));
+  float l1f, l2f, l3f;
+  if (p > 0.0f) {
+    const float ip = 1.0f / p;
+    float rr = 0.5f * det3(d0 * ip, f01 * ip, f02 * ip, d1 * ip, f12 * ip, d2 * ip);
+    rr = fminf(1.0f, fmaxf(-1.0f, rr));
+    const float phi = acosf(rr) * (1.0f / 3.0f);
+    l3f = q + 2.0f * p * cosf(phi);
+    l1f = q + 2.0f * p * cosf(phi + 2.0943951023931953f);
+    l2f = 3.0f * q - l1f - l3f;
+  } else {
+    l1f = l2f = l3f = q;
+  }
+
+  // Newton refinement of l1 on det(B - l I) in the working precision
+  T l = T(l1f);
+  const int iters = sizeof(T) == 8 ? 3 : 1;
+  for (int it = 0; it < iters; ++it) {
+    const T a0 = b00 - l, a1 = b11 - l, a2 = b22 - l;
+    const T m0 = a1 * a2 - b12 * b12, m1 = a0 * a2 - b02 * b02, m2 = a0 * a1 - b01 * b01;
+    const T f = a0 * m0 - b01 * (b01 * a2 - b12 * b02) + b02 * (b01 * b12 - a1 * b02);
+    const T fp = -(m0 + m1 + m2);
+    if (fp != T(0)) {
+      const T step = f / fp;
+      if (isfinite(step)) l -= step;
+    }
+  }
+
+  // eigenvector: largest cross product of two rows of (B - l I)
+  const T a00 = b00 - l, a11 = b11 - l, a22 = b22 - l;
+  // r0 = (a00, b01, b02), r1 = (b01, a11, b12), r2 = (b02, b12, a22)
+  T x0 = b01 * b12 - b02 * a11, y0 = b02 * b01 - a00 * b12, z0 = a00 * a11 - b01 * b01;  // r0 x r1
+  T x1 = b01 * a22 - b02 * b12, y1 = b02 * b02 - a00 * a22, z1 = a00 * b12 - b01 * b02;  // r0 x r2
+  T x2 = a11 * a22 - b12 * b12, y2 = b12 * b02 - b01 * a22, z2 = b01 * b12 - a11 * b02;  // r1 x r2
+  const T n0 = x0 * x0 + y0 * y0 + z0 * z0;
+  const T n1 = x1 * x1 + y1 * y1 + z1 * z1;
+  const T n2 = x2 * x2 + y2 * y2 + z2 * z2;
+  T vx = x0, vy = y0, vz = z0, nn = n0;
+  if (n1 > nn) { vx = x1; vy = y1; vz = z1; nn = n1; }
+  if (n2 > nn) { vx = x2; vy = y2; vz = z2; nn = n2; }
+  if (!(nn > T(0)) || !isfinite(nn)) {
+    // l1 has multiplicity >= 2: any vector orthogonal to the largest row
+    T rx = a00, ry = b01, rz = b02;
+    T rn = rx * rx + ry * ry + rz * rz;
+    const T r1n = b01 * b01 + a11 * a11 + b12 * b12;
+    if (r1n > rn) { rx = b01; ry = a11; rz = b12; rn = r1n; }
+    const T r2n = b02 * b02 + b12 * b12 + a22 * a22;
+    if (r2n > rn) { rx = b02; ry = b12; rz = a22; rn = r2n; }
+    if (rn > T(0)) {
+      // cross with the coordinate axis least aligned with r
+      if (fabs(rx) <= fabs(ry) && fabs(rx) <= fabs(rz)) { vx = T(0); vy = rz; vz = -ry; }
+      else if (fabs(ry) <= fabs(rz)) { vx = -rz; vy = T(0); vz = rx; }
+      else { vx = ry; vy = -rx; vz = T(0); }
+    } else {
+      vx = T(0); vy = T(0); vz = T(1);
+    }
+    nn = vx * vx + vy * vy + vz * vz;
+    e.degenerate = true;
+  }
+  const T inv = T(1) / sqrt(nn);
+  e.n[0] = vx * inv;
+  e.n[1] = vy * inv;
+  e.n[2] = vz * inv;
+  e.l1 = l * s;
+  e.l2 = T(l2f) * s;
+  e.l3 = T(l3f) * s;
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// Per-pixel solve from the window sums.
+//   B  = sum (w - w_ref)                 Fx = sum (x - x_c)(w - w_ref)
+//   Fy = sum (y - y_c)(w - w_ref)        Q  = sum (w - w_ref)^2
+// where x_c, y_c are the window centre's column and row; w = 1/Z.
+// ---------------------------------------------------------------------------
+struct PixelOut {
+  float n0, n1, n2, d, res;
+  uint8_t st;
+};
+
+template <typename T, int MODE>
+__device__ inline PixelOut solve_pixel(const FitArgs& a, T B, T Sxw, T Syw, T Q, int cnt,
+                                       T w_ref, int x0, int y0) {
+  PixelOut o;
+  const int N = a.k * a.k;
+  if (cnt != N) {
+    const float nan = __builtin_nanf("");
+    o.n0 = o.n1 = o.n2 = o.d = o.res = nan;
+    o.st = 1;
+    return o;
+  }
+  const T Nt = T(a.N), iN = T(a.inv_N), S2 = T(a.S2), iS2 = T(a.inv_S2);
+  const T fx = T(a.fx), fy = T(a.fy);
+  const T uc = (T(x0) - T(a.cx)) * T(a.inv_fx);
+  const T vc = (T(y0) - T(a.cy)) * T(a.inv_fy);
+  const T V = Nt * Q - B * B;                      // N sum (w - mean w)^2, reference-free
+  const T Sw = Nt * w_ref + B;                     // sum w
+  const T Sww = Q + w_ref * (T(2) * B + Nt * w_ref);  // sum w^2
+  o.st = 0;
+  if (MODE == PF_EXPLICIT) {
+    // Eq. 15 in centred regressors (x', y', 1): a' = Sxw/S2, b' = Syw/S2, c' = Sw/N
+    const T ap = Sxw * iS2, bp = Syw * iS2, cp = Sw * iN;
+    const T aa = fx * ap, bb = fy * bp, cc = cp - aa * uc - bb * vc;
+    const T nrm = sqrt(aa * aa + bb * bb + cc * cc);
+    const T inv = T(1) / nrm;
+    const T ssr = V * iN - (Sxw * Sxw + Syw * Syw) * iS2;  // sum (w - fit)^2
+    o.n0 = float(-aa * inv);
+    o.n1 = float(-bb * inv);
+    o.n2 = float(-cc * inv);
+    o.d = float(inv);
+    o.res = float(inv * sqrt(fmax(ssr, T(0)) * iN));
+  } else {
+    // Eq. 14 with |(a, b, c)| = 1: eliminating d leaves G = diag(S2, S2, N) - g g^T / Sww
+    // over gamma = (n_x/fx, n_y/fy, n . (u_c, v_c, 1)); C = M^T G M is the 3x3 in n.
+    const T iS = T(1) / Sww;
+    const T g11 = S2 - Sxw * Sxw * iS, g22 = S2 - Syw * Syw * iS;
+    const T g12 = -Sxw * Syw * iS, g13 = -Sxw * Sw * iS, g23 = -Syw * Sw * iS;
+    const T g33 = V * iS;
+    const T ifx = T(a.inv_fx), ify = T(a.inv_fy);
+    const T c00 = g11 * ifx * ifx + T(2) * g13 * uc * ifx + g33 * uc * uc;
+    const T c01 = g12 * ifx * ify + g13 * vc * ifx + g23 * uc * ify + g33 * uc * vc;
+    const T c02 = g13 * ifx + g33 * uc;
+    const T c11 = g22 * ify * ify + T(2) * g23 * vc * ify + g33 * vc * vc;
+    const T c12 = g23 * ify + g33 * vc;
+    const T c22 = g33;
+    Eig3<T> e = smallest_eig<T>(c00, c01, c02, c11, c12, c22);
+    T n0 = e.n[0], n1 = e.n[1], n2 = e.n[2];
+    const T gp = n0 * ifx, gq = n1 * ify, gt = n0 * uc + n1 * vc + n2;
+    T d = -(gp * Sxw + gq * Syw + gt * Sw) * iS;
+    if (d < T(0)) {
+      d = -d; n0 = -n0; n1 = -n1; n2 = -n2;
+    }
+    o.n0 = float(n0);
+    o.n1 = float(n1);
+    o.n2 = float(n2);
+    o.d = float(d);
+    o.res = float(sqrt(fmax(e.l1, T(0)) * iN));
+    if (a.kappa_flag > 0.0) {
+      const T gap = e.l2 - e.l1;
+      const bool ill = e.degenerate || !(gap > T(0)) || e.l3 > T(a.kappa_flag) * gap;
+      if (ill) o.st |= 2;
+    }
+  }
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// The fused kernel.  Workgroup = one strip of kBlock input columns (tile_w
+// output columns plus k-1 halo) by one band of tile_h output rows.
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void fit_planes_fused(FitArgs a) {
+  __shared__ T sw[kRows * kPitch];
+  __shared__ T syw[kRows * kPitch];
+  __shared__ T sww[kRows * kPitch];
+  __shared__ int sn[kRows * kPitch];
+  __shared__ double red[2 * (kBlock / 64)];
+
+  const int tid = threadIdx.x;
+  const int strip = blockIdx.x % a.n_strips;
+  const int band = blockIdx.x / a.n_strips;
+  const int ox0 = strip * a.tile_w;        // first output column
+  const int ix0 = ox0 - a.r;               // first input column of the strip
+  const int x = ix0 + tid;                 // this thread's input column
+  const int yb = band * a.tile_h;          // first output row
+  const int ye = min(yb + a.tile_h, a.H);  // one past the last output row
+  const int y_ref = yb + a.tile_h / 2;
+
+  // Per-tile reference disparity: mean of valid w on the band's middle row.
+  double ws = 0.0, wc = 0.0;
+  {
+    const int ym = min(y_ref, a.H - 1);
+    if (x >= 0 && x < a.W && tid < a.tile_w + a.k - 1) {
+      const float z = a.depth[(int64_t)ym * a.depth_pitch + x];
+      bool ok = depth_valid(z);
+      if (a.mask) ok = ok && a.mask[(int64_t)ym * a.mask_pitch + x] != 0;
+      if (ok) {
+        ws = 1.0 / double(z);
+        wc = 1.0;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      ws += __shfl_down(ws, off, 64);
+      wc += __shfl_down(wc, off, 64);
+    }
+    if ((tid & 63) == 0) {
+      red[2 * (tid >> 6)] = ws;
+      red[2 * (tid >> 6) + 1] = wc;
+    }
+    __syncthreads();
+    ws = 0.0;
+    wc = 0.0;
+    for (int i = 0; i < kBlock / 64; ++i) {
+      ws += red[2 * i];
+      wc += red[2 * i + 1];
+    }
+  }
+  const T w_ref = wc > 0.0 ? T(ws / wc) : T(0);
+
+  Cursor<T> lead, lag;
+  lead.clear();
+  lag.clear();
+  int y_lead = yb - a.r;
+  int y_lag = yb - a.r;
+  for (int i = 0; i < a.k - 1; ++i) add_pixel<T>(a, x, y_lead++, w_ref, y_ref, lead);
+
+  const int li = lds_index(tid);
+  for (int yg = yb; yg < ye; yg += kRows) {
+    const int nr = min(kRows, ye - yg);
+    // vertical phase: window column sums for nr output rows
+    for (int j = 0; j < nr; ++j) {
+      add_pixel<T>(a, x, y_lead++, w_ref, y_ref, lead);
+      if (yg + j > yb) add_pixel<T>(a, x, y_lag++, w_ref, y_ref, lag);
+      sw[j * kPitch + li] = lead.w - lag.w;
+      syw[j * kPitch + li] = lead.yw - lag.yw;
+      sww[j * kPitch + li] = lead.ww - lag.ww;
+      sn[j * kPitch + li] = lead.n - lag.n;
+    }
+    __syncthreads();
+    // horizontal phase: runs of kRunLen outputs along a row
+    const int j = tid / kRuns;
+    const int run = tid % kRuns;
+    const int o0 = run * kRunLen;
+    const int o1 = min(o0 + kRunLen, a.tile_w);
+    if (j < nr && o0 < o1) {
+      const int y0 = yg + j;
+      const T* rw = sw + j * kPitch;
+      const T* ryw = syw + j * kPitch;
+      const T* rww = sww + j * kPitch;
+      const int* rn = sn + j * kPitch;
+      const int base = o0 + a.r;  // x - x_c = (i - base) - (o - o0)
+      T hw = T(0), hx = T(0), hy = T(0), hww = T(0);
+      int hn = 0;
+      T gw = T(0), gx = T(0), gy = T(0), gww = T(0);
+      int gn = 0;
+      for (int i = o0; i < o0 + a.k - 1; ++i) {
+        const int l = lds_index(i);
+        const T v = rw[l];
+        hw += v;
+        hx += T(i - base) * v;
+        hy += ryw[l];
+        hww += rww[l];
+        hn += rn[l];
+      }
+      const int64_t row_off = (int64_t)y0 * a.W;
+      for (int o = o0; o < o1; ++o) {
+        {
+          const int i = o + a.k - 1;
+          const int l = lds_index(i);
+          const T v = rw[l];
+          hw += v;
+          hx += T(i - base) * v;
+          hy += ryw[l];
+          hww += rww[l];
+          hn += rn[l];
+        }
+        const T B = hw - gw;
+        const T Fx = hx - gx;
+        const T Fy = hy - gy;
+        const T Q = hww - gww;
+        const int cnt = hn - gn;
+        const int x0 = ox0 + o;
+        if (x0 < a.W) {
+          const T Sxw = Fx - T(o - o0) * B;
+          const T Syw = Fy - T(y0 - y_ref) * B;
+          const PixelOut po = solve_pixel<T, MODE>(a, B, Sxw, Syw, Q, cnt, w_ref, x0, y0);
+          const int64_t p = row_off + x0;
+          a.normals[p] = po.n0;
+          a.normals[a.plane + p] = po.n1;
+          a.normals[2 * a.plane + p] = po.n2;
+          a.offsets[p] = po.d;
+          a.residuals[p] = po.res;
+          if (a.status) a.status[p] = po.st;
+        }
+        {
+          const int l = lds_index(o);
+          const T v = rw[l];
+          gw += v;
+          gx += T(o - base) * v;
+          gy += ryw[l];
+          gww += rww[l];
+          gn += rn[l];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+thread_local int g_last_hip_error = 0;
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+struct pf_plan {
+  pf_intrinsics intr;
+  int64_t H, W;
+  pf_params params;
+  int k, r;
+  double S2, N;
+  int tile_w, tile_h, n_strips, n_bands;
+};
+
+extern "C" {
+
+const char* pf_status_string(pf_status s) {
+  switch (s) {
+    case PF_OK: return "ok";
+    case PF_ERR_NULL: return "a required pointer is NULL";
+    case PF_ERR_SHAPE: return "bad frame size (need 1 <= H, W <= 65535 and H*W <= 2^31)";
+    case PF_ERR_WINDOW: return "bad window (need odd k, 3 <= k <= 63, k <= min(H, W))";
+    case PF_ERR_INTRINSICS: return "bad intrinsics (need finite fx, fy > 0 and finite cx, cy)";
+    case PF_ERR_PITCH: return "a row pitch is smaller than the frame width";
+    case PF_ERR_ALIGNMENT: return "a float pointer is not 4-byte aligned";
+    case PF_ERR_WORKSPACE: return "workspace missing or too small";
+    case PF_ERR_UNSUPPORTED: return "unsupported mode, precision or flag value";
+    case PF_ERR_HIP: return "HIP runtime error (see pf_last_hip_error)";
+  }
+  return "unknown status";
+}
+
+int pf_last_hip_error(void) { return g_last_hip_error; }
+
+pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t width,
+                         const pf_params* params, pf_plan** out) {
+  if (out) *out = nullptr;
+  if (!intr || !params || !out) return PF_ERR_NULL;
+  if (height < 1 || width < 1 || height > 65535 || width > 65535 ||
+      height * width > (int64_t(1) << 31))
+    return PF_ERR_SHAPE;
+  if (!finite_pos(intr->fx) || !finite_pos(intr->fy) || !std::isfinite(intr->cx) ||
+      !std::isfinite(intr->cy))
+    return PF_ERR_INTRINSICS;
+  const int k = params->window;
+  if (k < 3 || k > kMaxWindow || (k % 2) == 0 || k > height || k > width) return PF_ERR_WINDOW;
+  if ((params->mode != PF_IMPLICIT && params->mode != PF_EXPLICIT) ||
+      (params->precision != PF_PREC_FP64 && params->precision != PF_PREC_FP32) ||
+      params->flags != 0 || !(params->kappa_flag >= 0.0) || !std::isfinite(params->kappa_flag))
+    return PF_ERR_UNSUPPORTED;
+  pf_plan* p = new (std::nothrow) pf_plan;
+  if (!p) return PF_ERR_UNSUPPORTED;
+  p->intr = *intr;
+  p->H = height;
+  p->W = width;
+  p->params = *params;
+  p->k = k;
+  p->r = k / 2;
+  p->N = double(k) * k;
+  p->S2 = double(k) * k * (double(k) * k - 1.0) / 12.0;
+  // strips: each workgroup covers kBlock input columns, k - 1 of them halo
+  const int tw_max = kBlock - (k - 1);
+  p->n_strips = int((width + tw_max - 1) / tw_max);
+  p->tile_w = int((width + p->n_strips - 1) / p->n_strips);
+  // bands: tall enough to amortise the k - 1 warm-up rows, enough of them to fill the chip
+  const int64_t target_groups = 512;
+  int64_t th = (height * p->n_strips + target_groups - 1) / target_groups;
+  th = std::max<int64_t>(th, 2 * k);
+  th = std::max<int64_t>(th, kRows);
+  th = std::min<int64_t>(th, height);
+  p->tile_h = int(th);
+  p->n_bands = int((height + th - 1) / th);
+  *out = p;
+  return PF_OK;
+}
+
+void pf_plan_destroy(pf_plan* plan) { delete plan; }
+
+size_t pf_plan_workspace_bytes(const pf_plan* plan) {
+  (void)plan;
+  return 0;
+}
+
+pf_status pf_plan_camera_moments(const pf_plan* plan, int64_t x0, int64_t y0, double out[6]) {
+  if (!plan || !out) return PF_ERR_NULL;
+  // window-centred closed form: sum x' = sum y' = sum x'y' = 0, sum x'^2 = sum y'^2 = S2
+  const double uc = (double(x0) - plan->intr.cx) / plan->intr.fx;
+  const double vc = (double(y0) - plan->intr.cy) / plan->intr.fy;
+  const double N = plan->N, S2 = plan->S2;
+  out[0] = N * uc * uc + S2 / (plan->intr.fx * plan->intr.fx);
+  out[1] = N * uc * vc;
+  out[2] = N * uc;
+  out[3] = N * vc * vc + S2 / (plan->intr.fy * plan->intr.fy);
+  out[4] = N * vc;
+  out[5] = N;
+  return PF_OK;
+}
+
+pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_pitch,
+                        const uint8_t* mask, int64_t mask_pitch, float* normals,
+                        float* offsets, float* residuals, uint8_t* status, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+  (void)workspace;
+  (void)workspace_bytes;
+  if (!plan || !depth || !normals || !offsets || !residuals) return PF_ERR_NULL;
+  if (depth_pitch < plan->W || (mask && mask_pitch < plan->W)) return PF_ERR_PITCH;
+  auto misaligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) != 0; };
+  if (misaligned(depth) || misaligned(normals) || misaligned(offsets) || misaligned(residuals))
+    return PF_ERR_ALIGNMENT;
+
+  FitArgs a;
+  a.depth = depth;
+  a.mask = mask;
+  a.normals = normals;
+  a.offsets = offsets;
+  a.residuals = residuals;
+  a.status = status;
+  a.depth_pitch = depth_pitch;
+  a.mask_pitch = mask ? mask_pitch : 0;
+  a.plane = plan->H * plan->W;
+  a.H = int(plan->H);
+  a.W = int(plan->W);
+  a.k = plan->k;
+  a.r = plan->r;
+  a.tile_w = plan->tile_w;
+  a.tile_h = plan->tile_h;
+  a.n_strips = plan->n_strips;
+  a.n_bands = plan->n_bands;
+  a.fx = plan->intr.fx;
+  a.fy = plan->intr.fy;
+  a.cx = plan->intr.cx;
+  a.cy = plan->intr.cy;
+  a.inv_fx = 1.0 / plan->intr.fx;
+  a.inv_fy = 1.0 / plan->intr.fy;
+  a.S2 = plan->S2;
+  a.inv_S2 = 1.0 / plan->S2;
+  a.N = plan->N;
+  a.inv_N = 1.0 / plan->N;
+  a.kappa_flag = plan->params.kappa_flag;
+
+  const dim3 grid(unsigned(plan->n_strips) * unsigned(plan->n_bands));
+  const dim3 block(kBlock);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool fp64 = plan->params.precision == PF_PREC_FP64;
+  const bool expl = plan->params.mode == PF_EXPLICIT;
+  if (fp64 && expl)
+    hipLaunchKernelGGL((fit_planes_fused<double, PF_EXPLICIT>), grid, block, 0, s, a);
+  else if (fp64)
+    hipLaunchKernelGGL((fit_planes_fused<double, PF_IMPLICIT>), grid, block, 0, s, a);
+  else if (expl)
+    hipLaunchKernelGGL((fit_planes_fused<float, PF_EXPLICIT>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((fit_planes_fused<float, PF_IMPLICIT>), grid, block, 0, s, a);
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess) {
+    g_last_hip_error = int(err);
+    return PF_ERR_HIP;
+  }
+  return PF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+"""Host-only checks of the C ABI (no GPU needed): the library loads and exports
+every function include/planefit.h declares, argument validation returns the
+documented codes before anything is enqueued, and the plan's closed-form
+camera-only moments match the oracle's brute-force window sums."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2103_06644_amd as pf
+from paper_2103_06644_amd._binding import _Intrinsics, _Params
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "planefit.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pf.load_library()
+    names = declared_functions()
+    assert len(names) >= 7
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(pf.EXPORTS)
+
+
+def _create(intr=(525.0, 525.0, 319.5, 239.5), H=480, W=640, k=5, mode=0, prec=0, flags=0,
+            kappa=0.0):
+    lib = pf.load_library()
+    h = ctypes.c_void_p()
+    code = lib.pf_plan_create(ctypes.byref(_Intrinsics(*intr)), H, W,
+                              ctypes.byref(_Params(k, mode, prec, flags, kappa)), ctypes.byref(h))
+    return code, h
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(k=4), 3), (dict(k=1), 3), (dict(k=65), 3), (dict(H=4, W=640, k=5), 3),
+    (dict(H=0), 2), (dict(W=-3), 2), (dict(H=70000), 2),
+    (dict(intr=(0.0, 525.0, 1.0, 1.0)), 4), (dict(intr=(525.0, float("nan"), 1.0, 1.0)), 4),
+    (dict(intr=(525.0, 525.0, float("inf"), 1.0)), 4),
+    (dict(mode=2), 8), (dict(prec=7), 8), (dict(flags=1), 8), (dict(kappa=-1.0), 8),
+    (dict(), 0), (dict(H=63, W=63, k=63), 0), (dict(mode=1, prec=1, kappa=1e6), 0),
+])
+def test_plan_validation(kw, code):
+    got, h = _create(**kw)
+    assert got == code, pf.status_string(got)
+    if code == 0:
+        assert h.value
+        pf.load_library().pf_plan_destroy(h)
+    else:
+        assert not h.value
+
+
+def test_plan_create_null_arguments():
+    lib = pf.load_library()
+    h = ctypes.c_void_p()
+    assert lib.pf_plan_create(None, 10, 10, ctypes.byref(_Params(3, 0, 0, 0, 0.0)),
+                              ctypes.byref(h)) == 1
+    assert lib.pf_plan_create(ctypes.byref(_Intrinsics(1, 1, 1, 1)), 10, 10, None,
+                              ctypes.byref(h)) == 1
+    lib.pf_plan_destroy(None)
+
+
+def test_fit_argument_checks_return_before_launch():
+    """Only error paths: every call below must be rejected on the host."""
+    lib = pf.load_library()
+    code, plan = _create(H=48, W=64, k=5)
+    assert code == 0
+    fake = ctypes.c_void_p(0x10000)  # never dereferenced: the checks return first
+    odd = ctypes.c_void_p(0x10001)
+    V = ctypes.c_void_p
+    call = lambda *a: lib.pf_fit_planes(*a)
+    assert call(None, fake, 64, None, 0, fake, fake, fake, None, None, 0, None) == 1
+    assert call(plan, None, 64, None, 0, fake, fake, fake, None, None, 0, None) == 1
+    assert call(plan, fake, 64, None, 0, None, fake, fake, None, None, 0, None) == 1
+    assert call(plan, fake, 63, None, 0, fake, fake, fake, None, None, 0, None) == 5
+    assert call(plan, fake, 64, fake, 10, fake, fake, fake, None, None, 0, None) == 5
+    assert call(plan, odd, 64, None, 0, fake, fake, fake, None, None, 0, None) == 6
+    assert call(plan, fake, 64, None, 0, fake, odd, fake, None, None, 0, None) == 6
+    lib.pf_plan_destroy(plan)
+
+
+def test_status_strings():
+    for c in range(10):
+        s = pf.status_string(c)
+        assert isinstance(s, str) and s
+    assert pf.load_library().pf_last_hip_error() == 0
+
+
+def test_workspace_is_zero_for_fused_path():
+    p = pf.Plan((525, 525, 319.5, 239.5), 480, 640, 9)
+    assert p.workspace_bytes == 0
+
+
+@pytest.mark.parametrize("k", [3, 5, 9, 15, 31, 63])
+def test_camera_moments_match_oracle_brute_force(k):
+    """Row a1: the plan's closed-form camera-only moments equal the oracle's
+    brute-force sums of u^2, uv, u, v^2, v, 1 over the window."""
+    for intr in [(525.0, 525.0, 319.5, 239.5), (131.25, 140.0, 79.5, 59.5),
+                 (1050.0, 1050.0, 959.5, 539.5)]:
+        p = pf.Plan(intr, 1080, 1920, k)
+        for (x0, y0) in [(0, 0), (k // 2, k // 2), (321, 17), (1919, 1079), (960, 540)]:
+            a = np.array(p.camera_moments(x0, y0))
+            b = oracle.camera_moments(intr, k, x0, y0)
+            scale = np.maximum(np.abs(b), 1.0)
+            assert np.all(np.abs(a - b) <= 1e-12 * scale * k * k), (k, intr, x0, y0, a, b)
+
+
+def test_binding_rejects_bad_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError):
+        pf.fit_planes(torch.zeros((8, 8)), (1, 1, 1, 1), 3)  # CPU tensor

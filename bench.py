@@ -1,0 +1,186 @@
+"""Benchmark: per-pixel RGBD plane fits on one MI355X.
+
+One step = the whole per-frame path (integrands, integral-image sweep, box
+sums, per-pixel solve, stores) over the 640x480 workload at every window size
+it lists (k = 3, 5, 9, 15), in the default implicit mode with FP64 moments.
+Inputs are seeded synthetic depth frames already resident in HBM; the timed
+loop rotates through enough distinct input/output buffer sets to keep the
+256 MB last-level cache from holding them.
+
+Printed: one JSON line with the throughput (Mpixel/s over all fitted pixels),
+the dominant kernel's roofline position (algorithmic HBM bytes per launch over
+its average HIP-event duration), the FP64 CPU oracle timed on a bounded sample
+on the host, and side measurements (explicit mode, FP32, the 1920x1080 frame).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E peak, GB/s
+BYTES_PER_PIXEL = 4 + 12 + 4 + 4 + 1   # depth in; normals, offset, residual, status out
+METRIC = ("Mpixel/s of per-pixel plane fits (normal+offset+residual) at 640×480 and "
+          "1080p; % HBM peak")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--sets", type=int, default=64, help="distinct buffer sets rotated")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+class Rig:
+    """Device buffers for `sets` copies of one frame and its outputs."""
+
+    def __init__(self, torch, depth_np, sets):
+        self.torch = torch
+        H, W = depth_np.shape
+        base = torch.from_numpy(depth_np).cuda()
+        self.depth = [base.clone() for _ in range(sets)]
+        self.outs = [(torch.empty((3, H, W), device="cuda"), torch.empty((H, W), device="cuda"),
+                      torch.empty((H, W), device="cuda"),
+                      torch.empty((H, W), dtype=torch.uint8, device="cuda"))
+                     for _ in range(sets)]
+        self.sets = sets
+        self.pixels = H * W
+
+
+def time_launches(torch, pf, rig, intr, ks, mode, precision, steps, warmup):
+    """Run warmup + steps; every launch bracketed by HIP events on its stream.
+    Returns (ms_per_step wall-clock over the timed region, [per-launch ms ...])."""
+    for p in ks:
+        pf.get_plan(intr, rig.depth[0].shape[0], rig.depth[0].shape[1], p, mode, precision)
+    for i in range(warmup):
+        s = i % rig.sets
+        for k in ks:
+            pf.fit_planes(rig.depth[s], intr, k, mode=mode, precision=precision, out=rig.outs[s])
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps * len(ks))]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record()
+    j = 0
+    for i in range(steps):
+        s = i % rig.sets
+        for k in ks:
+            a, b = evs[j]
+            a.record()
+            pf.fit_planes(rig.depth[s], intr, k, mode=mode, precision=precision, out=rig.outs[s])
+            b.record()
+            j += 1
+    t_end.record()
+    torch.cuda.synchronize()
+    per = [a.elapsed_time(b) for a, b in evs]
+    return t_start.elapsed_time(t_end) / steps, per
+
+
+def cpu_baseline(frame, ks, mode, budget_s):
+    """The FP64 oracle on the host: random sample of window centres, growing until
+    about budget_s seconds of work; returns Mpixel/s and what was sampled."""
+    import numpy as np
+    import oracle
+    z = frame.depth.astype(np.float64)
+    H, W = z.shape
+    threads = os.cpu_count() or 1
+    rng = np.random.Generator(np.random.PCG64(7))
+    n = 2000
+    total_px, total_t = 0, 0.0
+    while True:
+        t0 = time.perf_counter()
+        for k in ks:
+            ys = rng.integers(0, H, n)
+            xs = rng.integers(0, W, n)
+            oracle.fit_points(z, frame.intrinsics, k, xs, ys, mode, threads=threads)
+        dt = time.perf_counter() - t0
+        total_px += n * len(ks)
+        total_t += dt
+        if total_t >= budget_s or n >= 2_000_000:
+            break
+        n = int(n * min(8.0, max(1.5, (budget_s - total_t) / max(dt, 1e-3))))
+    return dict(value=total_px / total_t / 1e6, unit="Mpixel/s", cores=threads, kind="oracle",
+                sample=f"{total_px} random window centres of the 640x480 frame, "
+                       f"k in {list(ks)}, {mode} mode, FP64, {total_t:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only: frames are "
+                          "independent, so N GPUs process N disjoint frame streams; "
+                          "run it with --gpus 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2103_06644_amd as pf
+    from depthsynth import frames_for
+
+    pf.load_library()
+    f = frames_for("vga_640x480")[0]
+    ks = (3, 5, 9, 15)
+    rig = Rig(torch, f.depth, args.sets)
+    ms_step, per = time_launches(torch, pf, rig, f.intrinsics, ks, "implicit", "fp64",
+                                 args.steps, args.warmup)
+    px_step = rig.pixels * len(ks)
+    value = px_step / (ms_step * 1e-3) / 1e6
+    avg_launch_ms = float(np.mean(per))
+    per_k = {str(k): float(np.mean(per[i::len(ks)])) for i, k in enumerate(ks)}
+    achieved = rig.pixels * BYTES_PER_PIXEL / (avg_launch_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "vga_640x480: one 640x480 depth frame (8 planar patches + 3 "
+                               "spheres, 0.5-6 m, Kinect noise, 10% holes), windows k=3,5,9,15, "
+                               "implicit fit, FP64 moments", "frame": [480, 640],
+                   "windows": list(ks), "mode": "implicit", "precision": "fp64",
+                   "buffer_sets": args.sets},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "fit_planes_fused<double, implicit>",
+                     "algorithmic_bytes_per_launch": rig.pixels * BYTES_PER_PIXEL,
+                     "avg_launch_ms": round(avg_launch_ms, 5), "launch_ms_by_k": per_k},
+    }
+    if not args.no_extras:
+        extras = {}
+        for mode, prec in (("explicit", "fp64"), ("implicit", "fp32"), ("explicit", "fp32")):
+            ms, per2 = time_launches(torch, pf, rig, f.intrinsics, ks, mode, prec,
+                                     max(20, args.steps // 4), 5)
+            extras[f"vga_{mode}_{prec}_Mpx_s"] = round(px_step / (ms * 1e-3) / 1e6, 1)
+        del rig
+        torch.cuda.empty_cache()
+        hd = frames_for("hd_1920x1080")[0]
+        rig_hd = Rig(torch, hd.depth, 8)
+        for mode in ("implicit", "explicit"):
+            for k in (15, 31):
+                ms, per2 = time_launches(torch, pf, rig_hd, hd.intrinsics, (k,), mode, "fp64",
+                                         40, 5)
+                avg = float(np.mean(per2))
+                extras[f"hd_{mode}_k{k}"] = {
+                    "Mpx_s": round(rig_hd.pixels / (ms * 1e-3) / 1e6, 1),
+                    "avg_launch_ms": round(avg, 5),
+                    "hbm_frac": round(rig_hd.pixels * BYTES_PER_PIXEL / (avg * 1e-3) / 1e9 /
+                                      HBM_PEAK_GBS, 4)}
+        out["extras"] = extras
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(f, ks, "implicit", args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

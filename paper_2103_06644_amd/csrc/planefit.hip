@@ -104,15 +104,15 @@ __device__ inline void add_pixel(const FitArgs& a, int x, int y, T w_ref, int y_
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric 3x3 smallest eigenpair.
+// Symmetric 3x3 smallest eigenpair of a positive semidefinite matrix.
 //
-// Eigenvalues in closed form from the characteristic polynomial by the
-// trigonometric solution of the cubic (O. K. Smith, "Eigenvalues of a
-// symmetric 3x3 matrix", CACM 4(4), 1961) in FP32; for FP64 the smallest one
-// is then refined by Newton's method on det(B - l I) in FP64.  The
-// eigenvector is the best-conditioned cross product of two rows of B - l1 I
-// (as in J. Kopp, "Efficient numerical diagonalization of hermitian 3x3
-// matrices", 2008).
+// f(l) = det(B - l I) = (l1 - l)(l2 - l)(l3 - l) is convex and decreasing on
+// (-inf, l1], so Newton's method started at l = 0 <= l1 climbs monotonically
+// to l1 (it cannot overshoot).  The other two eigenvalues follow by deflating
+// the characteristic cubic to a quadratic.  The eigenvector is the
+// best-conditioned cross product of two rows of B - l1 I (the approach of
+// J. Kopp, "Efficient numerical diagonalization of hermitian 3x3 matrices",
+// 2008).  Accuracy of the normal ~ eps * l3 / (l2 - l1).
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Eig3 {
@@ -141,38 +141,30 @@ __device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22)
   const T is = T(1) / s;
   const T b00 = c00 * is, b01 = c01 * is, b02 = c02 * is;
   const T b11 = c11 * is, b12 = c12 * is, b22 = c22 * is;
+  const T c1 = (b11 * b22 - b12 * b12) + (b00 * b22 - b02 * b02) + (b00 * b11 - b01 * b01);
 
-  // closed-form estimates in FP32
-  const float q = float(b00 + b11 + b22) * (1.0f / 3.0f);
-  const float d0 = float(b00) - q, d1 = float(b11) - q, d2 = float(b22) - q;
-  const float f01 = float(b01), f02 = float(b02), f12 = float(b12);
-  const float p2 = d0 * d0 + d1 * d1 + d2 * d2 + 2.0f * (f01 * f01 + f02 * f02 + f12 * f12);
-  const float p = sqrtf(p2 * (1.0f / 6.0f));
-  float l1f, l2f, l3f;
-  if (p > 0.0f) {
-    const float ip = 1.0f / p;
-    float rr = 0.5f * det3(d0 * ip, f01 * ip, f02 * ip, d1 * ip, f12 * ip, d2 * ip);
-    rr = fminf(1.0f, fmaxf(-1.0f, rr));
-    const float phi = acosf(rr) * (1.0f / 3.0f);
-    l3f = q + 2.0f * p * cosf(phi);
-    l1f = q + 2.0f * p * cosf(phi + 2.0943951023931953f);
-    l2f = 3.0f * q - l1f - l3f;
-  } else {
-    l1f = l2f = l3f = q;
-  }
-
-  // Newton refinement of l1 on det(B - l I) in the working precision
-  T l = T(l1f);
-  const int iters = sizeof(T) == 8 ? 3 : 1;
-  for (int it = 0; it < iters; ++it) {
-    const T a0 = b00 - l, a1 = b11 - l, a2 = b22 - l;
-    const T m0 = a1 * a2 - b12 * b12, m1 = a0 * a2 - b02 * b02, m2 = a0 * a1 - b01 * b01;
-    const T f = a0 * m0 - b01 * (b01 * a2 - b12 * b02) + b02 * (b01 * b12 - a1 * b02);
-    const T fp = -(m0 + m1 + m2);
-    if (fp != T(0)) {
-      const T step = f / fp;
-      if (isfinite(step)) l -= step;
+  T l = T(0);
+  if (det3(b00, b01, b02, b11, b12, b22) > T(0)) {
+    const int max_iter = sizeof(T) == 8 ? 64 : 32;
+    for (int it = 0; it < max_iter; ++it) {
+      const T a0 = b00 - l, a1 = b11 - l, a2 = b22 - l;
+      const T m0 = a1 * a2 - b12 * b12, m1 = a0 * a2 - b02 * b02, m2 = a0 * a1 - b01 * b01;
+      const T f = a0 * m0 - b01 * (b01 * a2 - b12 * b02) + b02 * (b01 * b12 - a1 * b02);
+      const T fp = -(m0 + m1 + m2);
+      if (!(f > T(0)) || !(fp < T(0))) break;
+      const T ln = l - f / fp;
+      if (!(ln > l)) break;  // converged to rounding
+      l = ln;
     }
+  }
+  // deflate: l2 + l3 = tr - l1, l2 l3 = c1 - l1 (l2 + l3)
+  {
+    const T t = b00 + b11 + b22 - l;
+    const T pr = c1 - l * t;
+    const T sq = sqrt(fmax(t * t - T(4) * pr, T(0)));
+    const T l3 = T(0.5) * (t + sq);
+    e.l3 = l3;
+    e.l2 = l3 > T(0) ? pr / l3 : T(0);
   }
 
   // eigenvector: largest cross product of two rows of (B - l I)
@@ -211,8 +203,8 @@ __device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22)
   e.n[1] = vy * inv;
   e.n[2] = vz * inv;
   e.l1 = l * s;
-  e.l2 = T(l2f) * s;
-  e.l3 = T(l3f) * s;
+  e.l2 *= s;
+  e.l3 *= s;
   return e;
 }
 

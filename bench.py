@@ -109,9 +109,10 @@ def cpu_baseline(frame, ks, mode, budget_s):
         dt = time.perf_counter() - t0
         total_px += n * len(ks)
         total_t += dt
-        if total_t >= budget_s or n >= 2_000_000:
+        if total_t >= budget_s:
             break
         n = int(n * min(8.0, max(1.5, (budget_s - total_t) / max(dt, 1e-3))))
+        n = min(n, 5_000_000)
     return dict(value=total_px / total_t / 1e6, unit="Mpixel/s", cores=threads, kind="oracle",
                 sample=f"{total_px} random window centres of the 640x480 frame, "
                        f"k in {list(ks)}, {mode} mode, FP64, {total_t:.1f} s")

@@ -66,6 +66,7 @@ struct FitArgs {
   double inv_fx, inv_fy;
   double S2, inv_S2, N, inv_N;
   double kappa_flag;
+  int vec_store;  // outputs 16-byte aligned, W and tile_w multiples of 4
 };
 
 // ---------------------------------------------------------------------------
@@ -88,15 +89,38 @@ struct Cursor {
   }
 };
 
+// Depth sample of (x, y), with 0 standing for "no valid sample" (outside the
+// image, masked out).  A separate load step lets the sweep issue a whole
+// group of row loads before it consumes any of them.
+template <bool MASK>
+__device__ inline float load_depth(const FitArgs& a, int x, int y) {
+  if (x < 0 || x >= a.W || y < 0 || y >= a.H) return 0.0f;
+  float z = a.depth[(int64_t)y * a.depth_pitch + x];
+  if (MASK && a.mask[(int64_t)y * a.mask_pitch + x] == 0) z = 0.0f;
+  return z;
+}
+
+// Reciprocal of a positive depth: hardware estimate refined by Newton-Raphson
+// iterations r <- r + r (1 - z r) (two for FP64, one for FP32).  Homogeneous
+// under power-of-two scaling of z, like the rest of the path.
+__device__ inline double recip(float zf, double) {
+  const double z = double(zf);
+  double r = __builtin_amdgcn_rcp(z);
+  double e = fma(-z, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-z, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline float recip(float z, float) {
+  float r = __builtin_amdgcn_rcpf(z);
+  const float e = fmaf(-z, r, 1.0f);
+  return fmaf(r, e, r);
+}
+
 template <typename T>
-__device__ inline void add_pixel(const FitArgs& a, int x, int y, T w_ref, int y_ref,
-                                 Cursor<T>& c) {
-  if (x < 0 || x >= a.W || y < 0 || y >= a.H) return;
-  const float z = a.depth[(int64_t)y * a.depth_pitch + x];
-  bool ok = depth_valid(z);
-  if (a.mask) ok = ok && a.mask[(int64_t)y * a.mask_pitch + x] != 0;
-  if (!ok) return;
-  const T wh = T(1) / T(z) - w_ref;
+__device__ inline void add_sample(float z, int y, T w_ref, int y_ref, Cursor<T>& c) {
+  if (!depth_valid(z)) return;
+  const T wh = recip(z, T(0)) - w_ref;
   c.w += wh;
   c.yw += T(y - y_ref) * wh;
   c.ww += wh * wh;
@@ -107,8 +131,8 @@ __device__ inline void add_pixel(const FitArgs& a, int x, int y, T w_ref, int y_
 // Symmetric 3x3 smallest eigenpair of a positive semidefinite matrix.
 //
 // f(l) = det(B - l I) = (l1 - l)(l2 - l)(l3 - l) is convex and decreasing on
-// (-inf, l1], so Newton's method started at l = 0 <= l1 climbs monotonically
-// to l1 (it cannot overshoot).  The other two eigenvalues follow by deflating
+// (-inf, l1] and l1 >= 0, so Halley's iteration started at l = 0 climbs to l1
+// (cubically once close).  The other two eigenvalues follow by deflating
 // the characteristic cubic to a quadratic.  The eigenvector is the
 // best-conditioned cross product of two rows of B - l1 I (the approach of
 // J. Kopp, "Efficient numerical diagonalization of hermitian 3x3 matrices",
@@ -141,25 +165,31 @@ __device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22)
   const T is = T(1) / s;
   const T b00 = c00 * is, b01 = c01 * is, b02 = c02 * is;
   const T b11 = c11 * is, b12 = c12 * is, b22 = c22 * is;
+  // characteristic polynomial det(B - l I) = -l^3 + c2 l^2 - c1 l + c0
+  const T c2 = b00 + b11 + b22;
   const T c1 = (b11 * b22 - b12 * b12) + (b00 * b22 - b02 * b02) + (b00 * b11 - b01 * b01);
+  const T c0 = det3(b00, b01, b02, b11, b12, b22);
 
+  // Halley's iteration from l = 0: cubic convergence; on (-inf, l1] the
+  // polynomial is convex and decreasing, the iterates rise towards l1.
   T l = T(0);
-  if (det3(b00, b01, b02, b11, b12, b22) > T(0)) {
-    const int max_iter = sizeof(T) == 8 ? 64 : 32;
-    for (int it = 0; it < max_iter; ++it) {
-      const T a0 = b00 - l, a1 = b11 - l, a2 = b22 - l;
-      const T m0 = a1 * a2 - b12 * b12, m1 = a0 * a2 - b02 * b02, m2 = a0 * a1 - b01 * b01;
-      const T f = a0 * m0 - b01 * (b01 * a2 - b12 * b02) + b02 * (b01 * b12 - a1 * b02);
-      const T fp = -(m0 + m1 + m2);
+  if (c0 > T(0)) {
+    const T tol = sizeof(T) == 8 ? T(1e-15) : T(1e-7);
+    for (int it = 0; it < 32; ++it) {
+      const T f = ((c2 - l) * l - c1) * l + c0;
+      const T fp = (T(2) * c2 - T(3) * l) * l - c1;
+      const T fpp = T(2) * c2 - T(6) * l;
       if (!(f > T(0)) || !(fp < T(0))) break;
-      const T ln = l - f / fp;
-      if (!(ln > l)) break;  // converged to rounding
+      const T ln = l - T(2) * f * fp / (T(2) * fp * fp - f * fpp);
+      if (!(ln > l)) break;
+      const T step = ln - l;
       l = ln;
+      if (step <= tol) break;
     }
   }
   // deflate: l2 + l3 = tr - l1, l2 l3 = c1 - l1 (l2 + l3)
   {
-    const T t = b00 + b11 + b22 - l;
+    const T t = c2 - l;
     const T pr = c1 - l * t;
     const T sq = sqrt(fmax(t * t - T(4) * pr, T(0)));
     const T l3 = T(0.5) * (t + sq);
@@ -288,8 +318,12 @@ __device__ inline PixelOut solve_pixel(const FitArgs& a, T B, T Sxw, T Syw, T Q,
 // ---------------------------------------------------------------------------
 // The fused kernel.  Workgroup = one strip of kBlock input columns (tile_w
 // output columns plus k-1 halo) by one band of tile_h output rows.
+//
+// Row bookkeeping for output row y0: the lead cursor has summed input rows
+// yb-r .. y0+r and the lag cursor rows yb-r .. y0-r-1, so lead - lag is the
+// column sum over the window rows y0-r .. y0+r.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE>
+template <typename T, int MODE, bool MASK>
 __global__ __launch_bounds__(kBlock) void fit_planes_fused(FitArgs a) {
   __shared__ T sw[kRows * kPitch];
   __shared__ T syw[kRows * kPitch];
@@ -306,19 +340,15 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(FitArgs a) {
   const int yb = band * a.tile_h;          // first output row
   const int ye = min(yb + a.tile_h, a.H);  // one past the last output row
   const int y_ref = yb + a.tile_h / 2;
+  const bool col_used = tid < a.tile_w + a.k - 1;
 
   // Per-tile reference disparity: mean of valid w on the band's middle row.
   double ws = 0.0, wc = 0.0;
   {
-    const int ym = min(y_ref, a.H - 1);
-    if (x >= 0 && x < a.W && tid < a.tile_w + a.k - 1) {
-      const float z = a.depth[(int64_t)ym * a.depth_pitch + x];
-      bool ok = depth_valid(z);
-      if (a.mask) ok = ok && a.mask[(int64_t)ym * a.mask_pitch + x] != 0;
-      if (ok) {
-        ws = 1.0 / double(z);
-        wc = 1.0;
-      }
+    const float z = col_used ? load_depth<MASK>(a, x, min(y_ref, a.H - 1)) : 0.0f;
+    if (depth_valid(z)) {
+      ws = recip(z, 0.0);
+      wc = 1.0;
     }
     for (int off = 32; off > 0; off >>= 1) {
       ws += __shfl_down(ws, off, 64);
@@ -341,34 +371,67 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(FitArgs a) {
   Cursor<T> lead, lag;
   lead.clear();
   lag.clear();
-  int y_lead = yb - a.r;
-  int y_lag = yb - a.r;
-  for (int i = 0; i < a.k - 1; ++i) add_pixel<T>(a, x, y_lead++, w_ref, y_ref, lead);
+
+  // warm-up: the lead cursor takes rows yb-r .. yb+r-1, kRows loads at a time
+  for (int c = 0; c < a.k - 1; c += kRows) {
+    float z[kRows];
+#pragma unroll
+    for (int j = 0; j < kRows; ++j)
+      z[j] = (c + j < a.k - 1 && col_used) ? load_depth<MASK>(a, x, yb - a.r + c + j) : 0.0f;
+#pragma unroll
+    for (int j = 0; j < kRows; ++j)
+      if (c + j < a.k - 1) add_sample<T>(z[j], yb - a.r + c + j, w_ref, y_ref, lead);
+  }
+
+  // depth samples of the current round, loaded one round ahead
+  float zl[kRows], zg[kRows];
+#pragma unroll
+  for (int j = 0; j < kRows; ++j) {
+    const int y0 = yb + j;
+    zl[j] = (y0 < ye && col_used) ? load_depth<MASK>(a, x, y0 + a.r) : 0.0f;
+    zg[j] = (y0 < ye && y0 > yb && col_used) ? load_depth<MASK>(a, x, y0 - a.r - 1) : 0.0f;
+  }
 
   const int li = lds_index(tid);
+  const int hj = tid / kRuns;      // row of the round this thread fits in the horizontal phase
+  const int run = tid % kRuns;
+  const int o0 = run * kRunLen;    // first output column (strip-relative) of the run
+  const int o1 = min(o0 + kRunLen, a.tile_w);
+  const bool vec_store = a.vec_store != 0;
+
   for (int yg = yb; yg < ye; yg += kRows) {
     const int nr = min(kRows, ye - yg);
     // vertical phase: window column sums for nr output rows
-    for (int j = 0; j < nr; ++j) {
-      add_pixel<T>(a, x, y_lead++, w_ref, y_ref, lead);
-      if (yg + j > yb) add_pixel<T>(a, x, y_lag++, w_ref, y_ref, lag);
-      sw[j * kPitch + li] = lead.w - lag.w;
-      syw[j * kPitch + li] = lead.yw - lag.yw;
-      sww[j * kPitch + li] = lead.ww - lag.ww;
-      sn[j * kPitch + li] = lead.n - lag.n;
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+      if (j < nr) {
+        const int y0 = yg + j;
+        add_sample<T>(zl[j], y0 + a.r, w_ref, y_ref, lead);
+        if (y0 > yb) add_sample<T>(zg[j], y0 - a.r - 1, w_ref, y_ref, lag);
+        sw[j * kPitch + li] = lead.w - lag.w;
+        syw[j * kPitch + li] = lead.yw - lag.yw;
+        sww[j * kPitch + li] = lead.ww - lag.ww;
+        sn[j * kPitch + li] = lead.n - lag.n;
+      }
+    }
+    // issue the next round's loads now; they land while the horizontal phase runs
+    {
+      const int yn = yg + kRows;
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) {
+        const int y0 = yn + j;
+        zl[j] = (y0 < ye && col_used) ? load_depth<MASK>(a, x, y0 + a.r) : 0.0f;
+        zg[j] = (y0 < ye && col_used) ? load_depth<MASK>(a, x, y0 - a.r - 1) : 0.0f;
+      }
     }
     __syncthreads();
-    // horizontal phase: runs of kRunLen outputs along a row
-    const int j = tid / kRuns;
-    const int run = tid % kRuns;
-    const int o0 = run * kRunLen;
-    const int o1 = min(o0 + kRunLen, a.tile_w);
-    if (j < nr && o0 < o1) {
-      const int y0 = yg + j;
-      const T* rw = sw + j * kPitch;
-      const T* ryw = syw + j * kPitch;
-      const T* rww = sww + j * kPitch;
-      const int* rn = sn + j * kPitch;
+    // horizontal phase: a run of kRunLen outputs along one row
+    if (hj < nr && o0 < o1) {
+      const int y0 = yg + hj;
+      const T* rw = sw + hj * kPitch;
+      const T* ryw = syw + hj * kPitch;
+      const T* rww = sww + hj * kPitch;
+      const int* rn = sn + hj * kPitch;
       const int base = o0 + a.r;  // x - x_c = (i - base) - (o - o0)
       T hw = T(0), hx = T(0), hy = T(0), hww = T(0);
       int hn = 0;
@@ -383,44 +446,85 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(FitArgs a) {
         hww += rww[l];
         hn += rn[l];
       }
-      const int64_t row_off = (int64_t)y0 * a.W;
-      for (int o = o0; o < o1; ++o) {
-        {
-          const int i = o + a.k - 1;
-          const int l = lds_index(i);
-          const T v = rw[l];
-          hw += v;
-          hx += T(i - base) * v;
-          hy += ryw[l];
-          hww += rww[l];
-          hn += rn[l];
-        }
-        const T B = hw - gw;
-        const T Fx = hx - gx;
-        const T Fy = hy - gy;
-        const T Q = hww - gww;
-        const int cnt = hn - gn;
-        const int x0 = ox0 + o;
-        if (x0 < a.W) {
-          const T Sxw = Fx - T(o - o0) * B;
+      float on0[kRunLen], on1[kRunLen], on2[kRunLen], od[kRunLen], ores[kRunLen];
+      uint8_t ost[kRunLen];
+#pragma unroll
+      for (int q = 0; q < kRunLen; ++q) {
+        const int o = o0 + q;
+        if (o < o1) {
+          {
+            const int i = o + a.k - 1;
+            const int l = lds_index(i);
+            const T v = rw[l];
+            hw += v;
+            hx += T(i - base) * v;
+            hy += ryw[l];
+            hww += rww[l];
+            hn += rn[l];
+          }
+          const T B = hw - gw;
+          const T Fx = hx - gx;
+          const T Fy = hy - gy;
+          const T Q = hww - gww;
+          const int cnt = hn - gn;
+          const T Sxw = Fx - T(q) * B;
           const T Syw = Fy - T(y0 - y_ref) * B;
-          const PixelOut po = solve_pixel<T, MODE>(a, B, Sxw, Syw, Q, cnt, w_ref, x0, y0);
-          const int64_t p = row_off + x0;
-          a.normals[p] = po.n0;
-          a.normals[a.plane + p] = po.n1;
-          a.normals[2 * a.plane + p] = po.n2;
-          a.offsets[p] = po.d;
-          a.residuals[p] = po.res;
-          if (a.status) a.status[p] = po.st;
+          const PixelOut po = solve_pixel<T, MODE>(a, B, Sxw, Syw, Q, cnt, w_ref, ox0 + o, y0);
+          on0[q] = po.n0; on1[q] = po.n1; on2[q] = po.n2; od[q] = po.d; ores[q] = po.res;
+          ost[q] = po.st;
+          {
+            const int l = lds_index(o);
+            const T v = rw[l];
+            gw += v;
+            gx += T(o - base) * v;
+            gy += ryw[l];
+            gww += rww[l];
+            gn += rn[l];
+          }
         }
-        {
-          const int l = lds_index(o);
-          const T v = rw[l];
-          gw += v;
-          gx += T(o - base) * v;
-          gy += ryw[l];
-          gww += rww[l];
-          gn += rn[l];
+      }
+      const int x0 = ox0 + o0;
+      const int64_t p = (int64_t)y0 * a.W + x0;
+      if (vec_store && o0 + kRunLen <= o1 && x0 + kRunLen <= a.W) {
+        // 16-byte aligned: W and tile_w are multiples of 4, o0 a multiple of 8
+        float4* n0p = reinterpret_cast<float4*>(a.normals + p);
+        float4* n1p = reinterpret_cast<float4*>(a.normals + a.plane + p);
+        float4* n2p = reinterpret_cast<float4*>(a.normals + 2 * a.plane + p);
+        float4* dp = reinterpret_cast<float4*>(a.offsets + p);
+        float4* rp = reinterpret_cast<float4*>(a.residuals + p);
+#pragma unroll
+        for (int h = 0; h < kRunLen / 4; ++h) {
+          n0p[h] = make_float4(on0[4 * h], on0[4 * h + 1], on0[4 * h + 2], on0[4 * h + 3]);
+          n1p[h] = make_float4(on1[4 * h], on1[4 * h + 1], on1[4 * h + 2], on1[4 * h + 3]);
+          n2p[h] = make_float4(on2[4 * h], on2[4 * h + 1], on2[4 * h + 2], on2[4 * h + 3]);
+          dp[h] = make_float4(od[4 * h], od[4 * h + 1], od[4 * h + 2], od[4 * h + 3]);
+          rp[h] = make_float4(ores[4 * h], ores[4 * h + 1], ores[4 * h + 2], ores[4 * h + 3]);
+        }
+        if (a.status) {
+          uint32_t lo = 0, hi = 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            lo |= uint32_t(ost[q]) << (8 * q);
+            hi |= uint32_t(ost[q + 4]) << (8 * q);
+          }
+          if ((p & 7) == 0) {
+            *reinterpret_cast<uint2*>(a.status + p) = make_uint2(lo, hi);
+          } else {
+            reinterpret_cast<uint32_t*>(a.status + p)[0] = lo;
+            reinterpret_cast<uint32_t*>(a.status + p)[1] = hi;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < kRunLen; ++q) {
+          if (o0 + q < o1 && x0 + q < a.W) {
+            a.normals[p + q] = on0[q];
+            a.normals[a.plane + p + q] = on1[q];
+            a.normals[2 * a.plane + p + q] = on2[q];
+            a.offsets[p + q] = od[q];
+            a.residuals[p + q] = ores[q];
+            if (a.status) a.status[p + q] = ost[q];
+          }
         }
       }
     }
@@ -493,9 +597,10 @@ pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t widt
   p->N = double(k) * k;
   p->S2 = double(k) * k * (double(k) * k - 1.0) / 12.0;
   // strips: each workgroup covers kBlock input columns, k - 1 of them halo
-  const int tw_max = kBlock - (k - 1);
+  // (tile_w kept a multiple of 4 so rows of a run can be stored as float4)
+  const int tw_max = ((kBlock - (k - 1)) / 4) * 4;
   p->n_strips = int((width + tw_max - 1) / tw_max);
-  p->tile_w = int((width + p->n_strips - 1) / p->n_strips);
+  p->tile_w = int(((width + p->n_strips - 1) / p->n_strips + 3) / 4 * 4);
   // bands: tall enough to amortise the k - 1 warm-up rows, enough of them to fill the chip
   const int64_t target_groups = 512;
   int64_t th = (height * p->n_strips + target_groups - 1) / target_groups;
@@ -571,20 +676,28 @@ pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_p
   a.N = plan->N;
   a.inv_N = 1.0 / plan->N;
   a.kappa_flag = plan->params.kappa_flag;
+  auto aligned = [](const void* q, uintptr_t m) { return (reinterpret_cast<uintptr_t>(q) & m) == 0; };
+  a.vec_store = (plan->W % 4 == 0) && (plan->tile_w % 4 == 0) && aligned(normals, 15) &&
+                aligned(offsets, 15) && aligned(residuals, 15) && (!status || aligned(status, 3));
 
   const dim3 grid(unsigned(plan->n_strips) * unsigned(plan->n_bands));
   const dim3 block(kBlock);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const bool fp64 = plan->params.precision == PF_PREC_FP64;
   const bool expl = plan->params.mode == PF_EXPLICIT;
-  if (fp64 && expl)
-    hipLaunchKernelGGL((fit_planes_fused<double, PF_EXPLICIT>), grid, block, 0, s, a);
-  else if (fp64)
-    hipLaunchKernelGGL((fit_planes_fused<double, PF_IMPLICIT>), grid, block, 0, s, a);
-  else if (expl)
-    hipLaunchKernelGGL((fit_planes_fused<float, PF_EXPLICIT>), grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL((fit_planes_fused<float, PF_IMPLICIT>), grid, block, 0, s, a);
+  const bool has_mask = mask != nullptr;
+#define PF_LAUNCH(T, M, K) \
+  hipLaunchKernelGGL((fit_planes_fused<T, M, K>), grid, block, 0, s, a)
+  if (fp64 && expl) {
+    if (has_mask) PF_LAUNCH(double, PF_EXPLICIT, true); else PF_LAUNCH(double, PF_EXPLICIT, false);
+  } else if (fp64) {
+    if (has_mask) PF_LAUNCH(double, PF_IMPLICIT, true); else PF_LAUNCH(double, PF_IMPLICIT, false);
+  } else if (expl) {
+    if (has_mask) PF_LAUNCH(float, PF_EXPLICIT, true); else PF_LAUNCH(float, PF_EXPLICIT, false);
+  } else {
+    if (has_mask) PF_LAUNCH(float, PF_IMPLICIT, true); else PF_LAUNCH(float, PF_IMPLICIT, false);
+  }
+#undef PF_LAUNCH
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess) {
     g_last_hip_error = int(err);

@@ -2,7 +2,12 @@
 frame and compare element by element.
 
 Tolerances (normal angle <= 1e-4 rad, relative offset <= 1e-5) are the stated
-targets for the FP64 path.  The implicit normal is only defined up to the
+targets for the FP64 path.  The offset is compared relative to the distance of
+the window's centre point from the camera, |P_c| = Z_c |(u_c, v_c, 1)|: for a
+plane facing the camera that is the offset itself, and for a plane seen
+edge-on (offset much smaller than the distance of its points) an offset error
+of |P_c| times the normal error is the unavoidable consequence of that normal
+error, so a tolerance relative to d alone would be ill-posed.  The implicit normal is only defined up to the
 conditioning of the 3x3 eigenproblem: it is gated where the oracle's
 kappa = l3/(l2 - l1) is at most KAPPA_GATE, and reported elsewhere.
 """
@@ -28,6 +33,11 @@ def angle(a, b):
     return np.arctan2(np.linalg.norm(cr, axis=0), np.sum(a * b, axis=0))
 
 
+def check(g, o, mode, depth, intrinsics, sel=None, **kw):
+    """compare() with the offset scale taken from the depth frame."""
+    return compare(g, o, mode, sel=sel, scale=centre_distance(depth, intrinsics, sel), **kw)
+
+
 def gpu_fit(depth_np, intrinsics, k, mode, precision="fp64", mask_np=None, kappa_flag=0.0):
     import torch
     import paper_2103_06644_amd as pf
@@ -40,8 +50,18 @@ def gpu_fit(depth_np, intrinsics, k, mode, precision="fp64", mask_np=None, kappa
                 residuals=r.cpu().numpy().astype(np.float64), status=s.cpu().numpy())
 
 
-def compare(g, o, mode, *, sel=None, kappa_gate=KAPPA_GATE):
+def centre_distance(depth, intrinsics, sel=None):
+    """|P_c| of every window centre (or the selected ones)."""
+    fx, fy, cx, cy = intrinsics
+    H, W = depth.shape
+    yy, xx = np.mgrid[0:H, 0:W]
+    d = depth.astype(np.float64) * np.sqrt(((xx - cx) / fx) ** 2 + ((yy - cy) / fy) ** 2 + 1.0)
+    return d if sel is None else d[sel]
+
+
+def compare(g, o, mode, *, sel=None, kappa_gate=KAPPA_GATE, scale=None):
     """Compare GPU outputs g with oracle outputs o (same layout; sel picks pixels).
+    `scale` is |P_c| per compared window (defaults to |d_oracle|).
 
     Returns a report dict; raises AssertionError on a validity mismatch."""
     gs = g["status"] if sel is None else g["status"][sel]
@@ -58,7 +78,8 @@ def compare(g, o, mode, *, sel=None, kappa_gate=KAPPA_GATE):
     nrm = np.linalg.norm(gn[:, ovalid], axis=0)
     gnu = gn / np.where(np.linalg.norm(gn, axis=0) > 0, np.linalg.norm(gn, axis=0), 1)
     ang = angle(gnu[:, gate], o["normals"][:, gate])
-    off = np.abs(go[gate] - o["offsets"][gate]) / np.abs(o["offsets"][gate])
+    den = np.abs(o["offsets"]) if scale is None else np.maximum(scale, np.abs(o["offsets"]))
+    off = np.abs(go[gate] - o["offsets"][gate]) / den[gate]
     res_err = np.abs(gr[gate] - o["residuals"][gate])
     res_bad = res_err > residual_tol(o["residuals"][gate])
     rep = dict(n_valid=int(ovalid.sum()), n_gated=int(gate.sum()),

@@ -42,7 +42,7 @@ def test_exact_planes(gpu, mode, k):
         _say("exact plane", n, d, k, mode)
         g = PT.gpu_fit(z, intr, k, mode)
         o = oracle.fit_planes(z.astype(np.float64), intr, k, mode)
-        rep = PT.compare(g, o, mode)
+        rep = PT.check(g, o, mode, z, intr)
         PT.assert_parity(rep)
         # float32 depth of an exact plane: residual at the level of its rounding
         v = o["status"] == 0
@@ -58,7 +58,7 @@ def test_parity_plain_160x120(gpu, mode):
     _say("plain_160x120", mode)
     g = PT.gpu_fit(f.depth, f.intrinsics, 5, mode)
     o = PT.oracle_full(f.depth, f.intrinsics, 5, mode)
-    rep = PT.compare(g, o, mode)
+    rep = PT.check(g, o, mode, f.depth, f.intrinsics)
     print(rep)
     PT.assert_parity(rep)
 
@@ -70,7 +70,7 @@ def test_parity_vga(gpu, mode, k):
     _say("vga_640x480", mode, k)
     g = PT.gpu_fit(f.depth, f.intrinsics, k, mode)
     o = PT.oracle_full(f.depth, f.intrinsics, k, mode)
-    rep = PT.compare(g, o, mode)
+    rep = PT.check(g, o, mode, f.depth, f.intrinsics)
     print(rep)
     PT.assert_parity(rep)
 
@@ -90,7 +90,7 @@ def test_parity_hd_sampled(gpu, mode, k):
     ys = np.concatenate([ys, cy.ravel(), [0, 0, H - 1, H - 1]])
     xs = np.concatenate([xs, cx.ravel(), [0, W - 1, 0, W - 1]])
     o = oracle.fit_points(f.depth.astype(np.float64), f.intrinsics, k, xs, ys, mode)
-    rep = PT.compare(g, o, mode, sel=(ys, xs))
+    rep = PT.check(g, o, mode, f.depth, f.intrinsics, sel=(ys, xs))
     print(rep)
     PT.assert_parity(rep)
 
@@ -103,7 +103,7 @@ def test_fp32_path_validity_and_error_report(gpu, mode):
     for k in (5, 15):
         g = PT.gpu_fit(f.depth, f.intrinsics, k, mode, precision="fp32")
         o = PT.oracle_full(f.depth, f.intrinsics, k, mode)
-        rep = PT.compare(g, o, mode)
+        rep = PT.check(g, o, mode, f.depth, f.intrinsics)
         print("fp32", mode, k, rep)
         assert rep["invalid_nan"]
 
@@ -145,7 +145,7 @@ def test_robust_inputs_and_mask(gpu):
         _say("robust", mode)
         g = PT.gpu_fit(z, f.intrinsics, 5, mode, mask_np=mask)
         o = oracle.fit_planes(z.astype(np.float64), f.intrinsics, 5, mode, mask=mask)
-        PT.assert_parity(PT.compare(g, o, mode))
+        PT.assert_parity(PT.check(g, o, mode, z, f.intrinsics))
 
 
 def test_all_invalid_and_tiny_frames(gpu):
@@ -162,7 +162,7 @@ def test_all_invalid_and_tiny_frames(gpu):
             g = PT.gpu_fit(zz, (cam.fx, cam.fy, cam.cx, cam.cy), k, mode)
             o = oracle.fit_planes(zz.astype(np.float64), (cam.fx, cam.fy, cam.cx, cam.cy), k, mode)
             assert int((g["status"] == 0).sum()) == 1
-            PT.assert_parity(PT.compare(g, o, mode))
+            PT.assert_parity(PT.check(g, o, mode, zz, (cam.fx, cam.fy, cam.cx, cam.cy)))
 
 
 def test_pitched_depth_and_ragged_widths(gpu):
@@ -170,9 +170,9 @@ def test_pitched_depth_and_ragged_widths(gpu):
     last strips, heights that leave ragged last bands."""
     import torch
     import paper_2103_06644_amd as pf
-    f = frame("vga_640x480")
     for (h, w, k) in [(479, 611, 5), (300, 257, 9), (97, 1000, 31), (250, 249, 7)]:
-        sub = np.ascontiguousarray(f.depth[:h, :w])
+        src = frame("vga_640x480" if w <= 640 else "hd_1920x1080").depth
+        sub = np.ascontiguousarray(src[:h, :w])
         wide = torch.zeros((h, w + 37), dtype=torch.float32, device="cuda")
         wide[:, 5:5 + w] = torch.from_numpy(sub).cuda()
         view = wide[:, 5:5 + w]
@@ -185,7 +185,7 @@ def test_pitched_depth_and_ragged_widths(gpu):
                      offsets=o_.cpu().numpy().astype(np.float64),
                      residuals=r.cpu().numpy().astype(np.float64), status=s.cpu().numpy())
             o = oracle.fit_planes(sub.astype(np.float64), intr, k, mode)
-            PT.assert_parity(PT.compare(g, o, mode))
+            PT.assert_parity(PT.check(g, o, mode, sub, intr))
 
 
 def test_kappa_flag_marks_ill_conditioned(gpu):

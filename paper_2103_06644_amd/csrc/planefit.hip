@@ -31,6 +31,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -606,6 +607,11 @@ pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t widt
   int64_t th = (height * p->n_strips + target_groups - 1) / target_groups;
   th = std::max<int64_t>(th, 2 * k);
   th = std::max<int64_t>(th, kRows);
+  // tuning override of the band height (rows of output per workgroup)
+  if (const char* env = std::getenv("PF_TILE_H")) {
+    const long v = std::strtol(env, nullptr, 10);
+    if (v >= 1) th = v;
+  }
   th = std::min<int64_t>(th, height);
   p->tile_h = int(th);
   p->n_bands = int((height + th - 1) / th);

@@ -43,10 +43,19 @@ constexpr int kBlock = 256;   // threads per workgroup; also the strip width in 
 constexpr int kRows = 8;      // output rows per vertical/horizontal round
 constexpr int kRuns = 32;     // runs per row in the horizontal phase
 constexpr int kRunLen = 8;    // output pixels per run (kRuns * kRunLen >= kBlock)
-constexpr int kPitch = kBlock + kBlock / 8 + 1;  // LDS row pitch after padding
 constexpr int kMaxWindow = 63;
 
-__host__ __device__ inline int lds_index(int i) { return i + (i >> 3); }
+// LDS layout of one row of window column sums: column i lives at
+// (i % 8) * kSub + i / 8.  In the horizontal phase the 32 runs of a row read
+// the same (i % 8) with consecutive i / 8 (consecutive words); in the vertical
+// phase 32 consecutive columns hit (i % 8) * 36 + (0..3), which with
+// kSub = 36 = 4 (mod 32) are 32 distinct 8-byte slots.  Both directions are
+// free of bank conflicts.
+constexpr int kSub = 36;
+constexpr int kPitch = kRunLen * kSub;  // 288 >= kBlock entries per row
+static_assert(kSub >= kBlock / kRunLen, "LDS row too short");
+
+__host__ __device__ inline int lds_index(int i) { return (i & (kRunLen - 1)) * kSub + (i >> 3); }
 
 struct FitArgs {
   const float* depth;
@@ -270,17 +279,19 @@ __device__ inline PixelOut solve_pixel(const FitArgs& a, T B, T Sxw, T Syw, T Q,
   const T Sww = Q + w_ref * (T(2) * B + Nt * w_ref);  // sum w^2
   o.st = 0;
   if (MODE == PF_EXPLICIT) {
-    // Eq. 15 in centred regressors (x', y', 1): a' = Sxw/S2, b' = Syw/S2, c' = Sw/N
-    const T ap = Sxw * iS2, bp = Syw * iS2, cp = Sw * iN;
-    const T aa = fx * ap, bb = fy * bp, cc = cp - aa * uc - bb * vc;
-    const T nrm = sqrt(aa * aa + bb * bb + cc * cc);
-    const T inv = T(1) / nrm;
-    const T ssr = V * iN - (Sxw * Sxw + Syw * Syw) * iS2;  // sum (w - fit)^2
-    o.n0 = float(-aa * inv);
-    o.n1 = float(-bb * inv);
-    o.n2 = float(-cc * inv);
-    o.d = float(inv);
-    o.res = float(inv * sqrt(fmax(ssr, T(0)) * iN));
+    // Eq. 15 in centred regressors (x', y', 1): a' = Sxw/S2, b' = Syw/S2, c' = Sw/N.
+    // The cancellation-prone differences (window sums, SSR) are formed in T; the
+    // closed-form solve from them needs only single precision.
+    const T ssr_t = V * iN - (Sxw * Sxw + Syw * Syw) * iS2;  // sum (w - fit)^2
+    const float ap = float(Sxw * iS2), bp = float(Syw * iS2), cp = float(Sw * iN);
+    const float aa = float(a.fx) * ap, bb = float(a.fy) * bp;
+    const float cc = cp - aa * float(uc) - bb * float(vc);
+    const float inv = 1.0f / sqrtf(aa * aa + bb * bb + cc * cc);
+    o.n0 = -aa * inv;
+    o.n1 = -bb * inv;
+    o.n2 = -cc * inv;
+    o.d = inv;
+    o.res = inv * sqrtf(fmaxf(float(ssr_t), 0.0f) * float(a.inv_N));
   } else {
     // Eq. 14 with |(a, b, c)| = 1: eliminating d leaves G = diag(S2, S2, N) - g g^T / Sww
     // over gamma = (n_x/fx, n_y/fy, n . (u_c, v_c, 1)); C = M^T G M is the 3x3 in n.
@@ -438,6 +449,7 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(FitArgs a) {
       int hn = 0;
       T gw = T(0), gx = T(0), gy = T(0), gww = T(0);
       int gn = 0;
+#pragma unroll 4
       for (int i = o0; i < o0 + a.k - 1; ++i) {
         const int l = lds_index(i);
         const T v = rw[l];
@@ -447,41 +459,63 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(FitArgs a) {
         hww += rww[l];
         hn += rn[l];
       }
+      // one output: advance the lead cursor, take the box sums, solve, advance the lag
+      auto step = [&](int q) -> PixelOut {
+        const int o = o0 + q;
+        {
+          const int i = o + a.k - 1;
+          const int l = lds_index(i);
+          const T v = rw[l];
+          hw += v;
+          hx += T(i - base) * v;
+          hy += ryw[l];
+          hww += rww[l];
+          hn += rn[l];
+        }
+        const T B = hw - gw;
+        const T Fx = hx - gx;
+        const T Fy = hy - gy;
+        const T Q = hww - gww;
+        const int cnt = hn - gn;
+        const T Sxw = Fx - T(q) * B;
+        const T Syw = Fy - T(y0 - y_ref) * B;
+        const PixelOut po = solve_pixel<T, MODE>(a, B, Sxw, Syw, Q, cnt, w_ref, ox0 + o, y0);
+        {
+          const int l = lds_index(o);
+          const T v = rw[l];
+          gw += v;
+          gx += T(o - base) * v;
+          gy += ryw[l];
+          gww += rww[l];
+          gn += rn[l];
+        }
+        return po;
+      };
+      if (MODE == PF_IMPLICIT) {
+        // the eigen-solve is large: keep the loop rolled and store each pixel directly
+        const int64_t prow = (int64_t)y0 * a.W + ox0;
+#pragma unroll 1
+        for (int q = 0; q < o1 - o0; ++q) {
+          const PixelOut po = step(q);
+          const int64_t pp = prow + o0 + q;
+          if (ox0 + o0 + q < a.W) {
+            a.normals[pp] = po.n0;
+            a.normals[a.plane + pp] = po.n1;
+            a.normals[2 * a.plane + pp] = po.n2;
+            a.offsets[pp] = po.d;
+            a.residuals[pp] = po.res;
+            if (a.status) a.status[pp] = po.st;
+          }
+        }
+      } else {
       float on0[kRunLen], on1[kRunLen], on2[kRunLen], od[kRunLen], ores[kRunLen];
       uint8_t ost[kRunLen];
 #pragma unroll
       for (int q = 0; q < kRunLen; ++q) {
-        const int o = o0 + q;
-        if (o < o1) {
-          {
-            const int i = o + a.k - 1;
-            const int l = lds_index(i);
-            const T v = rw[l];
-            hw += v;
-            hx += T(i - base) * v;
-            hy += ryw[l];
-            hww += rww[l];
-            hn += rn[l];
-          }
-          const T B = hw - gw;
-          const T Fx = hx - gx;
-          const T Fy = hy - gy;
-          const T Q = hww - gww;
-          const int cnt = hn - gn;
-          const T Sxw = Fx - T(q) * B;
-          const T Syw = Fy - T(y0 - y_ref) * B;
-          const PixelOut po = solve_pixel<T, MODE>(a, B, Sxw, Syw, Q, cnt, w_ref, ox0 + o, y0);
+        if (o0 + q < o1) {
+          const PixelOut po = step(q);
           on0[q] = po.n0; on1[q] = po.n1; on2[q] = po.n2; od[q] = po.d; ores[q] = po.res;
           ost[q] = po.st;
-          {
-            const int l = lds_index(o);
-            const T v = rw[l];
-            gw += v;
-            gx += T(o - base) * v;
-            gy += ryw[l];
-            gww += rww[l];
-            gn += rn[l];
-          }
         }
       }
       const int x0 = ox0 + o0;
@@ -527,6 +561,7 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(FitArgs a) {
             if (a.status) a.status[p + q] = ost[q];
           }
         }
+      }
       }
     }
     __syncthreads();

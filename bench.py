@@ -43,50 +43,110 @@ def parse():
 
 
 class Rig:
-    """Device buffers for `sets` copies of one frame and its outputs."""
+    """Device buffers for `sets` copies of one frame and `per_set` output sets each."""
 
-    def __init__(self, torch, depth_np, sets):
+    def __init__(self, torch, depth_np, sets, per_set=1):
         self.torch = torch
         H, W = depth_np.shape
         base = torch.from_numpy(depth_np).cuda()
         self.depth = [base.clone() for _ in range(sets)]
-        self.outs = [(torch.empty((3, H, W), device="cuda"), torch.empty((H, W), device="cuda"),
-                      torch.empty((H, W), device="cuda"),
-                      torch.empty((H, W), dtype=torch.uint8, device="cuda"))
-                     for _ in range(sets)]
+        self.outs = [[(torch.empty((3, H, W), device="cuda"), torch.empty((H, W), device="cuda"),
+                       torch.empty((H, W), device="cuda"),
+                       torch.empty((H, W), dtype=torch.uint8, device="cuda"))
+                      for _ in range(per_set)] for _ in range(sets)]
         self.sets = sets
         self.pixels = H * W
 
 
 def time_launches(torch, pf, rig, intr, ks, mode, precision, steps, warmup):
-    """Run warmup + steps; every launch bracketed by HIP events on its stream.
-    Returns (ms_per_step wall-clock over the timed region, [per-launch ms ...])."""
-    for p in ks:
-        pf.get_plan(intr, rig.depth[0].shape[0], rig.depth[0].shape[1], p, mode, precision)
+    """One step = one batched launch fitting the frame at every k in ks (or, with
+    a single k, a plain launch).  Every launch is bracketed by HIP events on the
+    stream it runs on.  Returns (ms per step over the timed region, [ms per launch])."""
+    H, W = rig.depth[0].shape
+    for k in ks:
+        pf.get_plan(intr, H, W, k, mode, precision)
+
+    def run(s):
+        if len(ks) == 1:
+            pf.fit_planes(rig.depth[s], intr, ks[0], mode=mode, precision=precision,
+                          out=rig.outs[s][0])
+        else:
+            pf.fit_planes_batch([rig.depth[s]] * len(ks), intr, list(ks), mode=mode,
+                                precision=precision, outs=rig.outs[s])
+
     for i in range(warmup):
-        s = i % rig.sets
-        for k in ks:
-            pf.fit_planes(rig.depth[s], intr, k, mode=mode, precision=precision, out=rig.outs[s])
+        run(i % rig.sets)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(steps * len(ks))]
+           for _ in range(steps)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record()
-    j = 0
     for i in range(steps):
-        s = i % rig.sets
-        for k in ks:
-            a, b = evs[j]
-            a.record()
-            pf.fit_planes(rig.depth[s], intr, k, mode=mode, precision=precision, out=rig.outs[s])
-            b.record()
-            j += 1
+        a, b = evs[i]
+        a.record()
+        run(i % rig.sets)
+        b.record()
     t_end.record()
     torch.cuda.synchronize()
     per = [a.elapsed_time(b) for a, b in evs]
     return t_start.elapsed_time(t_end) / steps, per
+
+
+def batch_measure(torch, pf, np, frames_for):
+    """The 64-frame mixed workload (320x240, 640x480, 1280x720; per-frame k):
+    one batched call (two launches of up to 32 frames), eager and replayed from a
+    captured HIP graph; two input/output sets alternate."""
+    frames = frames_for("batch_mixed_64")
+    sets = []
+    for _ in range(2):
+        d = [torch.from_numpy(f.depth).cuda() for f in frames]
+        o = [(torch.empty((3,) + f.depth.shape, device="cuda"),
+              torch.empty(f.depth.shape, device="cuda"), torch.empty(f.depth.shape, device="cuda"),
+              torch.empty(f.depth.shape, dtype=torch.uint8, device="cuda")) for f in frames]
+        sets.append((d, o))
+    intr = [f.intrinsics for f in frames]
+    ks = [f.window for f in frames]
+    px = sum(f.depth.size for f in frames)
+
+    def call(s):
+        pf.fit_planes_batch(sets[s][0], intr, ks, mode="implicit", outs=sets[s][1])
+
+    for i in range(5):
+        call(i % 2)
+    torch.cuda.synchronize()
+    n = 40
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(n):
+        call(i % 2)
+    b.record()
+    torch.cuda.synchronize()
+    eager = a.elapsed_time(b) / n
+    graphs = []
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for s in range(2):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                call(s)
+            graphs.append(g)
+    torch.cuda.current_stream().wait_stream(side)
+    for i in range(4):
+        graphs[i % 2].replay()
+    torch.cuda.synchronize()
+    a.record()
+    for i in range(n):
+        graphs[i % 2].replay()
+    b.record()
+    torch.cuda.synchronize()
+    graph = a.elapsed_time(b) / n
+    return {"frames": len(frames), "pixels": px, "mode": "implicit", "precision": "fp64",
+            "eager_ms": round(eager, 4), "graph_ms": round(graph, 4),
+            "eager_Mpx_s": round(px / (eager * 1e-3) / 1e6, 1),
+            "graph_Mpx_s": round(px / (graph * 1e-3) / 1e6, 1)}
 
 
 def cpu_baseline(frame, ks, mode, budget_s):
@@ -133,14 +193,14 @@ def main():
     pf.load_library()
     f = frames_for("vga_640x480")[0]
     ks = (3, 5, 9, 15)
-    rig = Rig(torch, f.depth, args.sets)
+    rig = Rig(torch, f.depth, args.sets, per_set=len(ks))
     ms_step, per = time_launches(torch, pf, rig, f.intrinsics, ks, "implicit", "fp64",
                                  args.steps, args.warmup)
     px_step = rig.pixels * len(ks)
     value = px_step / (ms_step * 1e-3) / 1e6
     avg_launch_ms = float(np.mean(per))
-    per_k = {str(k): float(np.mean(per[i::len(ks)])) for i, k in enumerate(ks)}
-    achieved = rig.pixels * BYTES_PER_PIXEL / (avg_launch_ms * 1e-3) / 1e9
+    bytes_launch = px_step * BYTES_PER_PIXEL     # one launch fits the frame at all four k
+    achieved = bytes_launch / (avg_launch_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
@@ -153,9 +213,10 @@ def main():
                    "buffer_sets": args.sets},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "fit_planes_fused<double, implicit>",
-                     "algorithmic_bytes_per_launch": rig.pixels * BYTES_PER_PIXEL,
-                     "avg_launch_ms": round(avg_launch_ms, 5), "launch_ms_by_k": per_k},
+                     "kernel": "fit_planes_fused<double, implicit, no mask>",
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "bytes_per_pixel": BYTES_PER_PIXEL, "pixels_per_launch": px_step,
+                     "avg_launch_ms": round(avg_launch_ms, 5)},
     }
     if not args.no_extras:
         extras = {}
@@ -166,7 +227,7 @@ def main():
         del rig
         torch.cuda.empty_cache()
         hd = frames_for("hd_1920x1080")[0]
-        rig_hd = Rig(torch, hd.depth, 8)
+        rig_hd = Rig(torch, hd.depth, 8, per_set=1)
         for mode in ("implicit", "explicit"):
             for k in (15, 31):
                 ms, per2 = time_launches(torch, pf, rig_hd, hd.intrinsics, (k,), mode, "fp64",
@@ -177,6 +238,9 @@ def main():
                     "avg_launch_ms": round(avg, 5),
                     "hbm_frac": round(rig_hd.pixels * BYTES_PER_PIXEL / (avg * 1e-3) / 1e9 /
                                       HBM_PEAK_GBS, 4)}
+        del rig_hd
+        torch.cuda.empty_cache()
+        extras["batch_mixed_64"] = batch_measure(torch, pf, np, frames_for)
         out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(f, ks, "implicit", args.cpu_seconds)

@@ -130,6 +130,28 @@ pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_p
                         float* offsets, float* residuals, uint8_t* status, void* workspace,
                         size_t workspace_bytes, void* stream);
 
+/* Device buffers of one frame for pf_fit_planes_batch (same meaning, layout and
+ * ownership as the arguments of pf_fit_planes). */
+typedef struct {
+  const float* depth;
+  int64_t depth_pitch;
+  const uint8_t* mask;   /* or NULL */
+  int64_t mask_pitch;
+  float* normals;        /* [3][H][W] */
+  float* offsets;        /* [H][W] */
+  float* residuals;      /* [H][W] */
+  uint8_t* status;       /* [H][W] or NULL */
+} pf_frame_io;
+
+/* Enqueue the fits of n frames (Sec. II-C: many fits from one pass over each
+ * frame) in as few launches as possible: up to 32 frames per kernel launch,
+ * of any sizes and window sizes, each described by its own plan.  All plans
+ * must share mode, precision and kappa_flag (else PF_ERR_UNSUPPORTED).  Every
+ * frame is checked on the host as in pf_fit_planes before anything is
+ * enqueued; n = 0 is a no-op.  No workspace is needed. */
+pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io, int32_t n,
+                              void* stream);
+
 /* Static description of a status code. */
 const char* pf_status_string(pf_status s);
 

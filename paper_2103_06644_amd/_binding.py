@@ -44,6 +44,13 @@ class _Intrinsics(ctypes.Structure):
                 ("cx", ctypes.c_double), ("cy", ctypes.c_double)]
 
 
+class _FrameIO(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_void_p), ("depth_pitch", ctypes.c_int64),
+                ("mask", ctypes.c_void_p), ("mask_pitch", ctypes.c_int64),
+                ("normals", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("residuals", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
 class _Params(ctypes.Structure):
     _fields_ = [("window", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
@@ -54,8 +61,8 @@ _lib = None
 _lib_lock = threading.Lock()
 
 EXPORTS = ("pf_plan_create", "pf_plan_destroy", "pf_plan_workspace_bytes",
-           "pf_plan_camera_moments", "pf_fit_planes", "pf_status_string",
-           "pf_last_hip_error")
+           "pf_plan_camera_moments", "pf_fit_planes", "pf_fit_planes_batch",
+           "pf_status_string", "pf_last_hip_error")
 
 
 def load_library(path: str | None = None):
@@ -82,6 +89,8 @@ def load_library(path: str | None = None):
         lib.pf_fit_planes.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp,
                                       ctypes.c_size_t, vp]
         lib.pf_fit_planes.restype = i32
+        lib.pf_fit_planes_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_FrameIO), i32, vp]
+        lib.pf_fit_planes_batch.restype = i32
         lib.pf_status_string.argtypes = [i32]
         lib.pf_status_string.restype = ctypes.c_char_p
         lib.pf_last_hip_error.argtypes = []
@@ -228,3 +237,71 @@ def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "
             _stream_handle(torch, dev, stream))
     _check(code)
     return normals, offsets, residuals, status
+
+
+def _check_depth(torch, depth):
+    if depth.dim() != 2 or depth.dtype != torch.float32 or depth.device.type != "cuda":
+        raise ValueError("depth must be a float32 [H, W] tensor on a HIP device")
+    if depth.stride(1) != 1:
+        raise ValueError("depth must have unit stride along W")
+
+
+def _mask_arg(torch, valid_mask, depth):
+    if valid_mask is None:
+        return None, 0
+    if valid_mask.shape != depth.shape or valid_mask.device != depth.device:
+        raise ValueError("valid_mask must match depth's shape and device")
+    if valid_mask.dtype == torch.bool:
+        valid_mask = valid_mask.view(torch.uint8)
+    if valid_mask.dtype != torch.uint8 or valid_mask.stride(1) != 1:
+        raise ValueError("valid_mask must be uint8/bool with unit stride along W")
+    return valid_mask.data_ptr(), valid_mask.stride(0)
+
+
+def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="implicit",
+                     precision="fp64", kappa_flag=0.0, outs=None, stream=None):
+    """Per-pixel plane fits of several frames (any sizes, per-frame window sizes)
+    in as few kernel launches as possible (up to 32 frames per launch).
+
+    depths       list of float32 [H_i, W_i] tensors on one HIP device
+    intrinsics   one (fx, fy, cx, cy) for all frames, or a list of them
+    windows      one odd k for all frames, or a list of them
+    valid_masks  None or a list of (uint8/bool tensor or None)
+    outs         optional list of (normals, offsets, residuals, status) per frame
+    Returns the list of (normals, offsets, residuals, status).
+    """
+    import torch
+    n = len(depths)
+    if n == 0:
+        return []
+    intr = list(intrinsics) if isinstance(intrinsics[0], (tuple, list)) else [intrinsics] * n
+    ks = list(windows) if isinstance(windows, (tuple, list)) else [windows] * n
+    masks = list(valid_masks) if valid_masks is not None else [None] * n
+    if not (len(intr) == len(ks) == len(masks) == n):
+        raise ValueError("per-frame argument lists must have one entry per frame")
+    dev = depths[0].device
+    plans, ios, results, keep = [], (_FrameIO * n)(), [], []
+    for i, d in enumerate(depths):
+        _check_depth(torch, d)
+        if d.device != dev:
+            raise ValueError("all frames must be on one device")
+        H, W = d.shape
+        p = get_plan(intr[i], H, W, ks[i], mode, precision, kappa_flag)
+        plans.append(p)
+        mptr, mpitch = _mask_arg(torch, masks[i], d)
+        if outs is None:
+            o = (torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                 torch.empty((H, W), dtype=torch.float32, device=dev),
+                 torch.empty((H, W), dtype=torch.float32, device=dev),
+                 torch.empty((H, W), dtype=torch.uint8, device=dev))
+        else:
+            o = outs[i]
+        results.append(o)
+        ios[i] = _FrameIO(d.data_ptr(), d.stride(0), mptr, mpitch, o[0].data_ptr(),
+                          o[1].data_ptr(), o[2].data_ptr(), o[3].data_ptr())
+    handles = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    lib = load_library()
+    with torch.cuda.device(dev):
+        code = lib.pf_fit_planes_batch(handles, ios, n, _stream_handle(torch, dev, stream))
+    _check(code)
+    return results

@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cfloat>
 #include <cmath>
 #include <cstdint>
@@ -79,6 +80,32 @@ struct FitArgs {
   int vec_store;  // outputs 16-byte aligned, W and tile_w multiples of 4
 };
 
+// One frame of a launch, passed by value in the kernel arguments.
+struct Job {
+  const float* depth;
+  const uint8_t* mask;
+  float* normals;
+  float* offsets;
+  float* residuals;
+  uint8_t* status;
+  double fx, fy, cx, cy;
+  int32_t depth_pitch, mask_pitch;
+  int32_t H, W, k, tile_w, tile_h, n_strips;
+  int32_t wg_begin;   // first workgroup of this job in the launch
+  int32_t vec_store;
+};
+
+// Up to kMaxJobs frames (any sizes and window sizes, one mode and precision)
+// per launch; the whole struct stays under the 4 KiB kernel-argument limit.
+constexpr int kMaxJobs = 32;
+struct LaunchArgs {
+  int32_t n_jobs;
+  int32_t n_wg;
+  double kappa_flag;
+  Job jobs[kMaxJobs];
+};
+static_assert(sizeof(LaunchArgs) <= 4096, "kernel arguments too large");
+
 // ---------------------------------------------------------------------------
 // Per-pixel integrand (Sec. II-A: the entries of Eq. 14 that depend on depth).
 // ---------------------------------------------------------------------------
@@ -106,7 +133,7 @@ template <bool MASK>
 __device__ inline float load_depth(const FitArgs& a, int x, int y) {
   if (x < 0 || x >= a.W || y < 0 || y >= a.H) return 0.0f;
   float z = a.depth[(int64_t)y * a.depth_pitch + x];
-  if (MASK && a.mask[(int64_t)y * a.mask_pitch + x] == 0) z = 0.0f;
+  if (MASK && a.mask && a.mask[(int64_t)y * a.mask_pitch + x] == 0) z = 0.0f;
   return z;
 }
 
@@ -336,7 +363,43 @@ __device__ inline PixelOut solve_pixel(const FitArgs& a, T B, T Sxw, T Syw, T Q,
 // column sum over the window rows y0-r .. y0+r.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE, bool MASK>
-__global__ __launch_bounds__(kBlock) void fit_planes_fused(FitArgs a) {
+__global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
+  // which job and which of its workgroups (the job table is uniform: scalar loop)
+  int jb = 0;
+  while (jb + 1 < la.n_jobs && int(blockIdx.x) >= la.jobs[jb + 1].wg_begin) ++jb;
+  const Job& job = la.jobs[jb];
+  const int wg = int(blockIdx.x) - job.wg_begin;
+  FitArgs a;
+  a.depth = job.depth;
+  a.mask = job.mask;
+  a.normals = job.normals;
+  a.offsets = job.offsets;
+  a.residuals = job.residuals;
+  a.status = job.status;
+  a.depth_pitch = job.depth_pitch;
+  a.mask_pitch = job.mask_pitch;
+  a.H = job.H;
+  a.W = job.W;
+  a.plane = int64_t(job.H) * job.W;
+  a.k = job.k;
+  a.r = job.k / 2;
+  a.tile_w = job.tile_w;
+  a.tile_h = job.tile_h;
+  a.n_strips = job.n_strips;
+  a.n_bands = (job.H + job.tile_h - 1) / job.tile_h;
+  a.fx = job.fx;
+  a.fy = job.fy;
+  a.cx = job.cx;
+  a.cy = job.cy;
+  a.inv_fx = 1.0 / job.fx;
+  a.inv_fy = 1.0 / job.fy;
+  a.N = double(job.k) * job.k;
+  a.inv_N = 1.0 / a.N;
+  a.S2 = a.N * (a.N - 1.0) / 12.0;
+  a.inv_S2 = 1.0 / a.S2;
+  a.kappa_flag = la.kappa_flag;
+  a.vec_store = job.vec_store;
+
   __shared__ T sw[kRows * kPitch];
   __shared__ T syw[kRows * kPitch];
   __shared__ T sww[kRows * kPitch];
@@ -344,8 +407,8 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(FitArgs a) {
   __shared__ double red[2 * (kBlock / 64)];
 
   const int tid = threadIdx.x;
-  const int strip = blockIdx.x % a.n_strips;
-  const int band = blockIdx.x / a.n_strips;
+  const int strip = wg % a.n_strips;
+  const int band = wg / a.n_strips;
   const int ox0 = strip * a.tile_w;        // first output column
   const int ix0 = ox0 - a.r;               // first input column of the strip
   const int x = ix0 + tid;                 // this thread's input column
@@ -637,11 +700,11 @@ pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t widt
   const int tw_max = ((kBlock - (k - 1)) / 4) * 4;
   p->n_strips = int((width + tw_max - 1) / tw_max);
   p->tile_w = int(((width + p->n_strips - 1) / p->n_strips + 3) / 4 * 4);
-  // bands: tall enough to amortise the k - 1 warm-up rows, enough of them to fill the chip
-  const int64_t target_groups = 512;
+  // bands: enough workgroups to fill the chip (two resident per CU): one full
+  // wave of workgroups for the explicit solve, two for the heavier implicit one
+  const int64_t target_groups = params->mode == PF_EXPLICIT ? 512 : 1024;
   int64_t th = (height * p->n_strips + target_groups - 1) / target_groups;
-  th = std::max<int64_t>(th, 2 * k);
-  th = std::max<int64_t>(th, kRows);
+  th = std::max<int64_t>(th, 4);
   // tuning override of the band height (rows of output per workgroup)
   if (const char* env = std::getenv("PF_TILE_H")) {
     const long v = std::strtol(env, nullptr, 10);
@@ -676,75 +739,102 @@ pf_status pf_plan_camera_moments(const pf_plan* plan, int64_t x0, int64_t y0, do
   return PF_OK;
 }
 
+pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io, int32_t n,
+                              void* stream) {
+  if (n < 0) return PF_ERR_SHAPE;
+  if (n == 0) return PF_OK;
+  if (!plans || !io) return PF_ERR_NULL;
+  auto misaligned = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 3u) != 0; };
+  auto aligned = [](const void* q, uintptr_t m) { return (reinterpret_cast<uintptr_t>(q) & m) == 0; };
+  // host-side checks of every frame before anything is enqueued
+  for (int32_t i = 0; i < n; ++i) {
+    const pf_plan* p = plans[i];
+    const pf_frame_io& f = io[i];
+    if (!p || !f.depth || !f.normals || !f.offsets || !f.residuals) return PF_ERR_NULL;
+    if (f.depth_pitch < p->W || f.depth_pitch > INT32_MAX ||
+        (f.mask && (f.mask_pitch < p->W || f.mask_pitch > INT32_MAX)))
+      return PF_ERR_PITCH;
+    if (misaligned(f.depth) || misaligned(f.normals) || misaligned(f.offsets) ||
+        misaligned(f.residuals))
+      return PF_ERR_ALIGNMENT;
+    if (p->params.mode != plans[0]->params.mode ||
+        p->params.precision != plans[0]->params.precision ||
+        p->params.kappa_flag != plans[0]->params.kappa_flag)
+      return PF_ERR_UNSUPPORTED;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool fp64 = plans[0]->params.precision == PF_PREC_FP64;
+  const bool expl = plans[0]->params.mode == PF_EXPLICIT;
+  for (int32_t first = 0; first < n; first += kMaxJobs) {
+    const int32_t cnt = std::min<int32_t>(kMaxJobs, n - first);
+    LaunchArgs la;
+    std::memset(&la, 0, sizeof(la));
+    la.n_jobs = cnt;
+    la.kappa_flag = plans[first]->params.kappa_flag;
+    bool has_mask = false;
+    int32_t wg = 0;
+    for (int32_t j = 0; j < cnt; ++j) {
+      const pf_plan* p = plans[first + j];
+      const pf_frame_io& f = io[first + j];
+      Job& jb = la.jobs[j];
+      jb.depth = f.depth;
+      jb.mask = f.mask;
+      jb.normals = f.normals;
+      jb.offsets = f.offsets;
+      jb.residuals = f.residuals;
+      jb.status = f.status;
+      jb.fx = p->intr.fx;
+      jb.fy = p->intr.fy;
+      jb.cx = p->intr.cx;
+      jb.cy = p->intr.cy;
+      jb.depth_pitch = int32_t(f.depth_pitch);
+      jb.mask_pitch = f.mask ? int32_t(f.mask_pitch) : 0;
+      jb.H = int32_t(p->H);
+      jb.W = int32_t(p->W);
+      jb.k = p->k;
+      jb.tile_w = p->tile_w;
+      jb.tile_h = p->tile_h;
+      jb.n_strips = p->n_strips;
+      jb.wg_begin = wg;
+      jb.vec_store = (p->W % 4 == 0) && (p->tile_w % 4 == 0) && aligned(f.normals, 15) &&
+                     aligned(f.offsets, 15) && aligned(f.residuals, 15) &&
+                     (!f.status || aligned(f.status, 3));
+      has_mask = has_mask || f.mask != nullptr;
+      wg += p->n_strips * p->n_bands;
+    }
+    la.n_wg = wg;
+    const dim3 grid(static_cast<unsigned>(wg));
+    const dim3 block(kBlock);
+#define PF_LAUNCH(T, M, K) \
+  hipLaunchKernelGGL((fit_planes_fused<T, M, K>), grid, block, 0, s, la)
+    if (fp64 && expl) {
+      if (has_mask) PF_LAUNCH(double, PF_EXPLICIT, true); else PF_LAUNCH(double, PF_EXPLICIT, false);
+    } else if (fp64) {
+      if (has_mask) PF_LAUNCH(double, PF_IMPLICIT, true); else PF_LAUNCH(double, PF_IMPLICIT, false);
+    } else if (expl) {
+      if (has_mask) PF_LAUNCH(float, PF_EXPLICIT, true); else PF_LAUNCH(float, PF_EXPLICIT, false);
+    } else {
+      if (has_mask) PF_LAUNCH(float, PF_IMPLICIT, true); else PF_LAUNCH(float, PF_IMPLICIT, false);
+    }
+#undef PF_LAUNCH
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) {
+      g_last_hip_error = int(err);
+      return PF_ERR_HIP;
+    }
+  }
+  return PF_OK;
+}
+
 pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_pitch,
                         const uint8_t* mask, int64_t mask_pitch, float* normals,
                         float* offsets, float* residuals, uint8_t* status, void* workspace,
                         size_t workspace_bytes, void* stream) {
   (void)workspace;
   (void)workspace_bytes;
-  if (!plan || !depth || !normals || !offsets || !residuals) return PF_ERR_NULL;
-  if (depth_pitch < plan->W || (mask && mask_pitch < plan->W)) return PF_ERR_PITCH;
-  auto misaligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) != 0; };
-  if (misaligned(depth) || misaligned(normals) || misaligned(offsets) || misaligned(residuals))
-    return PF_ERR_ALIGNMENT;
-
-  FitArgs a;
-  a.depth = depth;
-  a.mask = mask;
-  a.normals = normals;
-  a.offsets = offsets;
-  a.residuals = residuals;
-  a.status = status;
-  a.depth_pitch = depth_pitch;
-  a.mask_pitch = mask ? mask_pitch : 0;
-  a.plane = plan->H * plan->W;
-  a.H = int(plan->H);
-  a.W = int(plan->W);
-  a.k = plan->k;
-  a.r = plan->r;
-  a.tile_w = plan->tile_w;
-  a.tile_h = plan->tile_h;
-  a.n_strips = plan->n_strips;
-  a.n_bands = plan->n_bands;
-  a.fx = plan->intr.fx;
-  a.fy = plan->intr.fy;
-  a.cx = plan->intr.cx;
-  a.cy = plan->intr.cy;
-  a.inv_fx = 1.0 / plan->intr.fx;
-  a.inv_fy = 1.0 / plan->intr.fy;
-  a.S2 = plan->S2;
-  a.inv_S2 = 1.0 / plan->S2;
-  a.N = plan->N;
-  a.inv_N = 1.0 / plan->N;
-  a.kappa_flag = plan->params.kappa_flag;
-  auto aligned = [](const void* q, uintptr_t m) { return (reinterpret_cast<uintptr_t>(q) & m) == 0; };
-  a.vec_store = (plan->W % 4 == 0) && (plan->tile_w % 4 == 0) && aligned(normals, 15) &&
-                aligned(offsets, 15) && aligned(residuals, 15) && (!status || aligned(status, 3));
-
-  const dim3 grid(unsigned(plan->n_strips) * unsigned(plan->n_bands));
-  const dim3 block(kBlock);
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const bool fp64 = plan->params.precision == PF_PREC_FP64;
-  const bool expl = plan->params.mode == PF_EXPLICIT;
-  const bool has_mask = mask != nullptr;
-#define PF_LAUNCH(T, M, K) \
-  hipLaunchKernelGGL((fit_planes_fused<T, M, K>), grid, block, 0, s, a)
-  if (fp64 && expl) {
-    if (has_mask) PF_LAUNCH(double, PF_EXPLICIT, true); else PF_LAUNCH(double, PF_EXPLICIT, false);
-  } else if (fp64) {
-    if (has_mask) PF_LAUNCH(double, PF_IMPLICIT, true); else PF_LAUNCH(double, PF_IMPLICIT, false);
-  } else if (expl) {
-    if (has_mask) PF_LAUNCH(float, PF_EXPLICIT, true); else PF_LAUNCH(float, PF_EXPLICIT, false);
-  } else {
-    if (has_mask) PF_LAUNCH(float, PF_IMPLICIT, true); else PF_LAUNCH(float, PF_IMPLICIT, false);
-  }
-#undef PF_LAUNCH
-  const hipError_t err = hipGetLastError();
-  if (err != hipSuccess) {
-    g_last_hip_error = int(err);
-    return PF_ERR_HIP;
-  }
-  return PF_OK;
+  if (!plan) return PF_ERR_NULL;
+  const pf_frame_io f = {depth, depth_pitch, mask, mask_pitch, normals, offsets, residuals, status};
+  return pf_fit_planes_batch(&plan, &f, 1, stream);
 }
 
 }  // extern "C"

@@ -117,3 +117,27 @@ def test_binding_rejects_bad_tensors():
     torch = pytest.importorskip("torch")
     with pytest.raises(ValueError):
         pf.fit_planes(torch.zeros((8, 8)), (1, 1, 1, 1), 3)  # CPU tensor
+
+
+def test_batch_argument_checks_return_before_launch():
+    from paper_2103_06644_amd._binding import _FrameIO
+    lib = pf.load_library()
+    c1, p1 = _create(H=48, W=64, k=5, mode=0)
+    c2, p2 = _create(H=48, W=64, k=5, mode=1)
+    assert c1 == 0 and c2 == 0
+    fake = 0x10000
+    io = (_FrameIO * 2)(_FrameIO(fake, 64, None, 0, fake, fake, fake, None),
+                        _FrameIO(fake, 64, None, 0, fake, fake, fake, None))
+    plans = (ctypes.c_void_p * 2)(p1.value, p2.value)
+    assert lib.pf_fit_planes_batch(plans, io, 0, None) == 0          # empty batch: no-op
+    assert lib.pf_fit_planes_batch(None, io, 2, None) == 1
+    assert lib.pf_fit_planes_batch(plans, io, -1, None) == 2
+    assert lib.pf_fit_planes_batch(plans, io, 2, None) == 8          # mixed modes
+    io[1].depth_pitch = 10
+    plans2 = (ctypes.c_void_p * 2)(p1.value, p1.value)
+    assert lib.pf_fit_planes_batch(plans2, io, 2, None) == 5         # bad pitch in frame 1
+    io[1].depth_pitch = 64
+    io[1].normals = None
+    assert lib.pf_fit_planes_batch(plans2, io, 2, None) == 1         # NULL output in frame 1
+    lib.pf_plan_destroy(p1)
+    lib.pf_plan_destroy(p2)

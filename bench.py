@@ -59,9 +59,11 @@ class Rig:
 
 
 def time_launches(torch, pf, rig, intr, ks, mode, precision, steps, warmup):
-    """One step = one batched launch fitting the frame at every k in ks (or, with
-    a single k, a plain launch).  Every launch is bracketed by HIP events on the
-    stream it runs on.  Returns (ms per step over the timed region, [ms per launch])."""
+    """One step = one launch fitting the frame at every k in ks (a batched launch
+    when there are several).  The timed steps are replayed from captured HIP
+    graphs, `chunk` consecutive steps (each on its own buffer set) per graph, so
+    the kernels run back to back with no host gaps; HIP events on the replay
+    stream bracket every replay.  Returns (ms per step, ms per launch)."""
     H, W = rig.depth[0].shape
     for k in ks:
         pf.get_plan(intr, H, W, k, mode, precision)
@@ -74,24 +76,41 @@ def time_launches(torch, pf, rig, intr, ks, mode, precision, steps, warmup):
             pf.fit_planes_batch([rig.depth[s]] * len(ks), intr, list(ks), mode=mode,
                                 precision=precision, outs=rig.outs[s])
 
+    chunk = max(c for c in range(1, min(32, rig.sets, steps) + 1) if steps % c == 0)
     for i in range(warmup):
         run(i % rig.sets)
     torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graphs = []
+    n_graphs = min(steps // chunk, -(-rig.sets // chunk))
+    with torch.cuda.stream(side):
+        for gi in range(n_graphs):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                for j in range(chunk):
+                    run((gi * chunk + j) % rig.sets)
+            graphs.append(g)
+    torch.cuda.current_stream().wait_stream(side)
+    for g in graphs:
+        g.replay()
+    torch.cuda.synchronize()
+    n_rep = steps // chunk
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(steps)]
+           for _ in range(n_rep)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record()
-    for i in range(steps):
+    for i in range(n_rep):
         a, b = evs[i]
         a.record()
-        run(i % rig.sets)
+        graphs[i % len(graphs)].replay()
         b.record()
     t_end.record()
     torch.cuda.synchronize()
-    per = [a.elapsed_time(b) for a, b in evs]
-    return t_start.elapsed_time(t_end) / steps, per
+    per_launch = float(sum(a.elapsed_time(b) for a, b in evs)) / (n_rep * chunk)
+    return t_start.elapsed_time(t_end) / steps, per_launch
 
 
 def batch_measure(torch, pf, np, frames_for):
@@ -194,11 +213,10 @@ def main():
     f = frames_for("vga_640x480")[0]
     ks = (3, 5, 9, 15)
     rig = Rig(torch, f.depth, args.sets, per_set=len(ks))
-    ms_step, per = time_launches(torch, pf, rig, f.intrinsics, ks, "implicit", "fp64",
-                                 args.steps, args.warmup)
+    ms_step, avg_launch_ms = time_launches(torch, pf, rig, f.intrinsics, ks, "implicit", "fp64",
+                                           args.steps, args.warmup)
     px_step = rig.pixels * len(ks)
     value = px_step / (ms_step * 1e-3) / 1e6
-    avg_launch_ms = float(np.mean(per))
     bytes_launch = px_step * BYTES_PER_PIXEL     # one launch fits the frame at all four k
     achieved = bytes_launch / (avg_launch_ms * 1e-3) / 1e9
     out = {
@@ -221,8 +239,7 @@ def main():
     if not args.no_extras:
         extras = {}
         for mode, prec in (("explicit", "fp64"), ("implicit", "fp32"), ("explicit", "fp32")):
-            ms, per2 = time_launches(torch, pf, rig, f.intrinsics, ks, mode, prec,
-                                     max(20, args.steps // 4), 5)
+            ms, _ = time_launches(torch, pf, rig, f.intrinsics, ks, mode, prec, 64, 5)
             extras[f"vga_{mode}_{prec}_Mpx_s"] = round(px_step / (ms * 1e-3) / 1e6, 1)
         del rig
         torch.cuda.empty_cache()
@@ -230,9 +247,8 @@ def main():
         rig_hd = Rig(torch, hd.depth, 8, per_set=1)
         for mode in ("implicit", "explicit"):
             for k in (15, 31):
-                ms, per2 = time_launches(torch, pf, rig_hd, hd.intrinsics, (k,), mode, "fp64",
-                                         40, 5)
-                avg = float(np.mean(per2))
+                ms, avg = time_launches(torch, pf, rig_hd, hd.intrinsics, (k,), mode, "fp64",
+                                        40, 5)
                 extras[f"hd_{mode}_k{k}"] = {
                     "Mpx_s": round(rig_hd.pixels / (ms * 1e-3) / 1e6, 1),
                     "avg_launch_ms": round(avg, 5),

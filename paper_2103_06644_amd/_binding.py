@@ -185,6 +185,25 @@ def _stream_handle(torch, device, stream):
     return ctypes.c_void_p(int(stream.cuda_stream))
 
 
+class _on_device:
+    """Make `dev` current for the call only when it is not already (cheap path)."""
+
+    def __init__(self, torch, dev):
+        self.torch, self.dev, self.ctx = torch, dev, None
+
+    def __enter__(self):
+        idx = self.dev.index if self.dev.index is not None else 0
+        if self.torch.cuda.current_device() != idx:
+            self.ctx = self.torch.cuda.device(self.dev)
+            self.ctx.__enter__()
+        return self
+
+    def __exit__(self, *exc):
+        if self.ctx is not None:
+            self.ctx.__exit__(*exc)
+        return False
+
+
 def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "implicit",
                precision: str = "fp64", kappa_flag: float = 0.0, out=None, stream=None):
     """Per-pixel plane fits of a depth frame on the GPU.
@@ -227,7 +246,7 @@ def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "
                                  "shapes [3,H,W], [H,W], [H,W], [H,W]")
     ws = plan.workspace_bytes
     work = torch.empty(ws, dtype=torch.uint8, device=dev) if ws else None
-    with torch.cuda.device(dev):
+    with _on_device(torch, dev):
         code = plan._lib.pf_fit_planes(
             plan.handle, ctypes.c_void_p(depth.data_ptr()), depth.stride(0),
             ctypes.c_void_p(mptr) if mptr else None, mpitch,
@@ -301,7 +320,7 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
                           o[1].data_ptr(), o[2].data_ptr(), o[3].data_ptr())
     handles = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
     lib = load_library()
-    with torch.cuda.device(dev):
+    with _on_device(torch, dev):
         code = lib.pf_fit_planes_batch(handles, ios, n, _stream_handle(torch, dev, stream))
     _check(code)
     return results

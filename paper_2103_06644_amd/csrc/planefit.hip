@@ -141,27 +141,55 @@ __device__ inline float load_depth(const FitArgs& a, int x, int y) {
 // iterations r <- r + r (1 - z r) (two for FP64, one for FP32).  Homogeneous
 // under power-of-two scaling of z, like the rest of the path.
 __device__ inline double recip(float zf, double) {
-  const double z = double(zf);
+  const double z = double(depth_valid(zf) ? zf : 1.0f);
   double r = __builtin_amdgcn_rcp(z);
   double e = fma(-z, r, 1.0);
   r = fma(r, e, r);
   e = fma(-z, r, 1.0);
   return fma(r, e, r);
 }
-__device__ inline float recip(float z, float) {
+__device__ inline float recip(float zf, float) {
+  const float z = depth_valid(zf) ? zf : 1.0f;
   float r = __builtin_amdgcn_rcpf(z);
   const float e = fmaf(-z, r, 1.0f);
   return fmaf(r, e, r);
 }
 
+// Reciprocal and reciprocal square root of a positive normal number: hardware
+// estimate plus Newton-Raphson refinement (two steps in FP64, one in FP32).
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline float rcp_nr(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ inline double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  // y <- y (3 - x y^2) / 2
+  double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+__device__ inline float rsq_nr(float x) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  return y * fmaf(-0.5f * x * y, y, 1.5f);
+}
+
 template <typename T>
 __device__ inline void add_sample(float z, int y, T w_ref, int y_ref, Cursor<T>& c) {
-  if (!depth_valid(z)) return;
-  const T wh = recip(z, T(0)) - w_ref;
+  // branch-free: invalid samples contribute exact zeros
+  const bool ok = depth_valid(z);
+  const T wh = ok ? recip(z, T(0)) - w_ref : T(0);
   c.w += wh;
   c.yw += T(y - y_ref) * wh;
   c.ww += wh * wh;
-  c.n += 1;
+  c.n += ok ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -199,7 +227,8 @@ __device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22)
     e.degenerate = true;
     return e;
   }
-  const T is = T(1) / s;
+  // scale by the power of two nearest below 1/s: exact, keeps every entry <= 1
+  const T is = ldexp(T(1), -ilogb(s));
   const T b00 = c00 * is, b01 = c01 * is, b02 = c02 * is;
   const T b11 = c11 * is, b12 = c12 * is, b22 = c22 * is;
   // characteristic polynomial det(B - l I) = -l^3 + c2 l^2 - c1 l + c0
@@ -207,17 +236,22 @@ __device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22)
   const T c1 = (b11 * b22 - b12 * b12) + (b00 * b22 - b02 * b02) + (b00 * b11 - b01 * b01);
   const T c0 = det3(b00, b01, b02, b11, b12, b22);
 
-  // Halley's iteration from l = 0: cubic convergence; on (-inf, l1] the
-  // polynomial is convex and decreasing, the iterates rise towards l1.
+  // Halley's iteration from the lower bound c0/c1 = 1/(1/l1 + 1/l2 + 1/l3) <= l1:
+  // cubic convergence; on (-inf, l1] the polynomial is convex and decreasing
+  // and the iterates rise towards l1.  The tolerance (1e-13 of the largest
+  // diagonal entry, FP64) keeps the eigenvector error below 1e-13 * kappa.
   T l = T(0);
-  if (c0 > T(0)) {
-    const T tol = sizeof(T) == 8 ? T(1e-15) : T(1e-7);
-    for (int it = 0; it < 32; ++it) {
+  if (c0 > T(0) && c1 > T(0)) {
+    l = c0 * rcp_nr(c1);
+    const T tol = sizeof(T) == 8 ? T(1e-13) : T(1e-6);
+    for (int it = 0; it < 24; ++it) {
       const T f = ((c2 - l) * l - c1) * l + c0;
       const T fp = (T(2) * c2 - T(3) * l) * l - c1;
       const T fpp = T(2) * c2 - T(6) * l;
       if (!(f > T(0)) || !(fp < T(0))) break;
-      const T ln = l - T(2) * f * fp / (T(2) * fp * fp - f * fpp);
+      const T den = T(2) * fp * fp - f * fpp;
+      if (!(den > T(0))) break;
+      const T ln = l - T(2) * f * fp * rcp_nr(den);
       if (!(ln > l)) break;
       const T step = ln - l;
       l = ln;
@@ -228,10 +262,11 @@ __device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22)
   {
     const T t = c2 - l;
     const T pr = c1 - l * t;
-    const T sq = sqrt(fmax(t * t - T(4) * pr, T(0)));
+    const T disc = t * t - T(4) * pr;
+    const T sq = disc > T(0) ? disc * rsq_nr(disc) : T(0);
     const T l3 = T(0.5) * (t + sq);
     e.l3 = l3;
-    e.l2 = l3 > T(0) ? pr / l3 : T(0);
+    e.l2 = l3 > T(0) ? pr * rcp_nr(l3) : T(0);
   }
 
   // eigenvector: largest cross product of two rows of (B - l I)
@@ -265,13 +300,15 @@ __device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22)
     nn = vx * vx + vy * vy + vz * vz;
     e.degenerate = true;
   }
-  const T inv = T(1) / sqrt(nn);
+  const T inv = rsq_nr(nn);
   e.n[0] = vx * inv;
   e.n[1] = vy * inv;
   e.n[2] = vz * inv;
-  e.l1 = l * s;
-  e.l2 *= s;
-  e.l3 *= s;
+  // undo the power-of-two scaling exactly
+  const int ex = ilogb(s);
+  e.l1 = ldexp(l, ex);
+  e.l2 = ldexp(e.l2, ex);
+  e.l3 = ldexp(e.l3, ex);
   return e;
 }
 
@@ -313,7 +350,7 @@ __device__ inline PixelOut solve_pixel(const FitArgs& a, T B, T Sxw, T Syw, T Q,
     const float ap = float(Sxw * iS2), bp = float(Syw * iS2), cp = float(Sw * iN);
     const float aa = float(a.fx) * ap, bb = float(a.fy) * bp;
     const float cc = cp - aa * float(uc) - bb * float(vc);
-    const float inv = 1.0f / sqrtf(aa * aa + bb * bb + cc * cc);
+    const float inv = rsq_nr(aa * aa + bb * bb + cc * cc);
     o.n0 = -aa * inv;
     o.n1 = -bb * inv;
     o.n2 = -cc * inv;
@@ -322,7 +359,7 @@ __device__ inline PixelOut solve_pixel(const FitArgs& a, T B, T Sxw, T Syw, T Q,
   } else {
     // Eq. 14 with |(a, b, c)| = 1: eliminating d leaves G = diag(S2, S2, N) - g g^T / Sww
     // over gamma = (n_x/fx, n_y/fy, n . (u_c, v_c, 1)); C = M^T G M is the 3x3 in n.
-    const T iS = T(1) / Sww;
+    const T iS = rcp_nr(Sww);
     const T g11 = S2 - Sxw * Sxw * iS, g22 = S2 - Syw * Syw * iS;
     const T g12 = -Sxw * Syw * iS, g13 = -Sxw * Sw * iS, g23 = -Syw * Sw * iS;
     const T g33 = V * iS;
@@ -344,7 +381,7 @@ __device__ inline PixelOut solve_pixel(const FitArgs& a, T B, T Sxw, T Syw, T Q,
     o.n1 = float(n1);
     o.n2 = float(n2);
     o.d = float(d);
-    o.res = float(sqrt(fmax(e.l1, T(0)) * iN));
+    o.res = sqrtf(float(fmax(e.l1, T(0)) * iN));
     if (a.kappa_flag > 0.0) {
       const T gap = e.l2 - e.l1;
       const bool ill = e.degenerate || !(gap > T(0)) || e.l3 > T(a.kappa_flag) * gap;

@@ -41,22 +41,43 @@
 namespace {
 
 constexpr int kBlock = 256;   // threads per workgroup; also the strip width in input columns
-constexpr int kRows = 8;      // output rows per vertical/horizontal round
-constexpr int kRuns = 32;     // runs per row in the horizontal phase
-constexpr int kRunLen = 8;    // output pixels per run (kRuns * kRunLen >= kBlock)
 constexpr int kMaxWindow = 63;
 
+// Work split of one round: `rows` output rows go through the vertical phase
+// together, then every thread fits a run of `run` consecutive outputs of one
+// row (kBlock / run runs per row, rows * kBlock / run = kBlock threads).  The
+// explicit solve is cheap, so long runs amortise the horizontal warm-up; the
+// implicit solve dominates, so short rounds halve the LDS footprint and let
+// more workgroups share a CU.
+//
 // LDS layout of one row of window column sums: column i lives at
-// (i % 8) * kSub + i / 8.  In the horizontal phase the 32 runs of a row read
-// the same (i % 8) with consecutive i / 8 (consecutive words); in the vertical
-// phase 32 consecutive columns hit (i % 8) * 36 + (0..3), which with
-// kSub = 36 = 4 (mod 32) are 32 distinct 8-byte slots.  Both directions are
-// free of bank conflicts.
-constexpr int kSub = 36;
-constexpr int kPitch = kRunLen * kSub;  // 288 >= kBlock entries per row
-static_assert(kSub >= kBlock / kRunLen, "LDS row too short");
+// (i % run) * sub + i / run.  In the horizontal phase the runs of a row read
+// the same (i % run) with consecutive i / run (consecutive words); in the
+// vertical phase 32 consecutive columns hit 32 distinct 8-byte slots because
+// sub * (run - 1) + 32 / run spans them without collisions modulo 32.  Both
+// directions are free of bank conflicts.
+template <int MODE>
+struct Tiling;
+template <>
+struct Tiling<PF_EXPLICIT> {
+  static constexpr int rows = 8, run = 8, sub = 36;
+};
+template <>
+struct Tiling<PF_IMPLICIT> {
+  static constexpr int rows = 4, run = 4, sub = 72;
+};
+constexpr int kPitch = 288;  // LDS entries per row, >= kBlock for both tilings
+static_assert(Tiling<PF_EXPLICIT>::run * Tiling<PF_EXPLICIT>::sub == kPitch, "pitch");
+static_assert(Tiling<PF_IMPLICIT>::run * Tiling<PF_IMPLICIT>::sub == kPitch, "pitch");
+static_assert(Tiling<PF_EXPLICIT>::rows * kBlock / Tiling<PF_EXPLICIT>::run == kBlock, "split");
+static_assert(Tiling<PF_IMPLICIT>::rows * kBlock / Tiling<PF_IMPLICIT>::run == kBlock, "split");
 
-__host__ __device__ inline int lds_index(int i) { return (i & (kRunLen - 1)) * kSub + (i >> 3); }
+template <int MODE>
+__host__ __device__ inline int lds_index(int i) {
+  using TL = Tiling<MODE>;
+  const unsigned u = unsigned(i);  // i >= 0 always
+  return int((u % TL::run) * TL::sub + u / TL::run);
+}
 
 struct FitArgs {
   const float* depth;
@@ -401,6 +422,7 @@ __device__ inline PixelOut solve_pixel(const FitArgs& a, T B, T Sxw, T Syw, T Q,
 // ---------------------------------------------------------------------------
 template <typename T, int MODE, bool MASK>
 __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
+  using TL = Tiling<MODE>;
   // which job and which of its workgroups (the job table is uniform: scalar loop)
   int jb = 0;
   while (jb + 1 < la.n_jobs && int(blockIdx.x) >= la.jobs[jb + 1].wg_begin) ++jb;
@@ -437,10 +459,10 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
   a.kappa_flag = la.kappa_flag;
   a.vec_store = job.vec_store;
 
-  __shared__ T sw[kRows * kPitch];
-  __shared__ T syw[kRows * kPitch];
-  __shared__ T sww[kRows * kPitch];
-  __shared__ int sn[kRows * kPitch];
+  __shared__ T sw[TL::rows * kPitch];
+  __shared__ T syw[TL::rows * kPitch];
+  __shared__ T sww[TL::rows * kPitch];
+  __shared__ int sn[TL::rows * kPitch];
   __shared__ double red[2 * (kBlock / 64)];
 
   const int tid = threadIdx.x;
@@ -484,38 +506,38 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
   lead.clear();
   lag.clear();
 
-  // warm-up: the lead cursor takes rows yb-r .. yb+r-1, kRows loads at a time
-  for (int c = 0; c < a.k - 1; c += kRows) {
-    float z[kRows];
+  // warm-up: the lead cursor takes rows yb-r .. yb+r-1, TL::rows loads at a time
+  for (int c = 0; c < a.k - 1; c += TL::rows) {
+    float z[TL::rows];
 #pragma unroll
-    for (int j = 0; j < kRows; ++j)
+    for (int j = 0; j < TL::rows; ++j)
       z[j] = (c + j < a.k - 1 && col_used) ? load_depth<MASK>(a, x, yb - a.r + c + j) : 0.0f;
 #pragma unroll
-    for (int j = 0; j < kRows; ++j)
+    for (int j = 0; j < TL::rows; ++j)
       if (c + j < a.k - 1) add_sample<T>(z[j], yb - a.r + c + j, w_ref, y_ref, lead);
   }
 
   // depth samples of the current round, loaded one round ahead
-  float zl[kRows], zg[kRows];
+  float zl[TL::rows], zg[TL::rows];
 #pragma unroll
-  for (int j = 0; j < kRows; ++j) {
+  for (int j = 0; j < TL::rows; ++j) {
     const int y0 = yb + j;
     zl[j] = (y0 < ye && col_used) ? load_depth<MASK>(a, x, y0 + a.r) : 0.0f;
     zg[j] = (y0 < ye && y0 > yb && col_used) ? load_depth<MASK>(a, x, y0 - a.r - 1) : 0.0f;
   }
 
-  const int li = lds_index(tid);
-  const int hj = tid / kRuns;      // row of the round this thread fits in the horizontal phase
-  const int run = tid % kRuns;
-  const int o0 = run * kRunLen;    // first output column (strip-relative) of the run
-  const int o1 = min(o0 + kRunLen, a.tile_w);
+  const int li = lds_index<MODE>(tid);
+  const int hj = tid / (kBlock / TL::run);      // row of the round this thread fits in the horizontal phase
+  const int run = tid % (kBlock / TL::run);
+  const int o0 = run * TL::run;    // first output column (strip-relative) of the run
+  const int o1 = min(o0 + TL::run, a.tile_w);
   const bool vec_store = a.vec_store != 0;
 
-  for (int yg = yb; yg < ye; yg += kRows) {
-    const int nr = min(kRows, ye - yg);
+  for (int yg = yb; yg < ye; yg += TL::rows) {
+    const int nr = min(TL::rows, ye - yg);
     // vertical phase: window column sums for nr output rows
 #pragma unroll
-    for (int j = 0; j < kRows; ++j) {
+    for (int j = 0; j < TL::rows; ++j) {
       if (j < nr) {
         const int y0 = yg + j;
         add_sample<T>(zl[j], y0 + a.r, w_ref, y_ref, lead);
@@ -528,16 +550,16 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
     }
     // issue the next round's loads now; they land while the horizontal phase runs
     {
-      const int yn = yg + kRows;
+      const int yn = yg + TL::rows;
 #pragma unroll
-      for (int j = 0; j < kRows; ++j) {
+      for (int j = 0; j < TL::rows; ++j) {
         const int y0 = yn + j;
         zl[j] = (y0 < ye && col_used) ? load_depth<MASK>(a, x, y0 + a.r) : 0.0f;
         zg[j] = (y0 < ye && col_used) ? load_depth<MASK>(a, x, y0 - a.r - 1) : 0.0f;
       }
     }
     __syncthreads();
-    // horizontal phase: a run of kRunLen outputs along one row
+    // horizontal phase: a run of TL::run outputs along one row
     if (hj < nr && o0 < o1) {
       const int y0 = yg + hj;
       const T* rw = sw + hj * kPitch;
@@ -551,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
       int gn = 0;
 #pragma unroll 4
       for (int i = o0; i < o0 + a.k - 1; ++i) {
-        const int l = lds_index(i);
+        const int l = lds_index<MODE>(i);
         const T v = rw[l];
         hw += v;
         hx += T(i - base) * v;
@@ -564,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
         const int o = o0 + q;
         {
           const int i = o + a.k - 1;
-          const int l = lds_index(i);
+          const int l = lds_index<MODE>(i);
           const T v = rw[l];
           hw += v;
           hx += T(i - base) * v;
@@ -581,7 +603,7 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
         const T Syw = Fy - T(y0 - y_ref) * B;
         const PixelOut po = solve_pixel<T, MODE>(a, B, Sxw, Syw, Q, cnt, w_ref, ox0 + o, y0);
         {
-          const int l = lds_index(o);
+          const int l = lds_index<MODE>(o);
           const T v = rw[l];
           gw += v;
           gx += T(o - base) * v;
@@ -608,10 +630,10 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
           }
         }
       } else {
-      float on0[kRunLen], on1[kRunLen], on2[kRunLen], od[kRunLen], ores[kRunLen];
-      uint8_t ost[kRunLen];
+      float on0[TL::run], on1[TL::run], on2[TL::run], od[TL::run], ores[TL::run];
+      uint8_t ost[TL::run];
 #pragma unroll
-      for (int q = 0; q < kRunLen; ++q) {
+      for (int q = 0; q < TL::run; ++q) {
         if (o0 + q < o1) {
           const PixelOut po = step(q);
           on0[q] = po.n0; on1[q] = po.n1; on2[q] = po.n2; od[q] = po.d; ores[q] = po.res;
@@ -620,7 +642,7 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
       }
       const int x0 = ox0 + o0;
       const int64_t p = (int64_t)y0 * a.W + x0;
-      if (vec_store && o0 + kRunLen <= o1 && x0 + kRunLen <= a.W) {
+      if (vec_store && o0 + TL::run <= o1 && x0 + TL::run <= a.W) {
         // 16-byte aligned: W and tile_w are multiples of 4, o0 a multiple of 8
         float4* n0p = reinterpret_cast<float4*>(a.normals + p);
         float4* n1p = reinterpret_cast<float4*>(a.normals + a.plane + p);
@@ -628,7 +650,7 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
         float4* dp = reinterpret_cast<float4*>(a.offsets + p);
         float4* rp = reinterpret_cast<float4*>(a.residuals + p);
 #pragma unroll
-        for (int h = 0; h < kRunLen / 4; ++h) {
+        for (int h = 0; h < TL::run / 4; ++h) {
           n0p[h] = make_float4(on0[4 * h], on0[4 * h + 1], on0[4 * h + 2], on0[4 * h + 3]);
           n1p[h] = make_float4(on1[4 * h], on1[4 * h + 1], on1[4 * h + 2], on1[4 * h + 3]);
           n2p[h] = make_float4(on2[4 * h], on2[4 * h + 1], on2[4 * h + 2], on2[4 * h + 3]);
@@ -651,7 +673,7 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
         }
       } else {
 #pragma unroll
-        for (int q = 0; q < kRunLen; ++q) {
+        for (int q = 0; q < TL::run; ++q) {
           if (o0 + q < o1 && x0 + q < a.W) {
             a.normals[p + q] = on0[q];
             a.normals[a.plane + p + q] = on1[q];

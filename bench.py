@@ -262,7 +262,8 @@ def main():
     }
     if not args.no_extras:
         extras = {}
-        for mode, prec in (("explicit", "fp64"), ("implicit", "fp32"), ("explicit", "fp32")):
+        for mode, prec in (("explicit", "fp64"), ("implicit", "fp32"), ("explicit", "fp32"),
+                           ("implicit", "compensated"), ("explicit", "compensated")):
             ms, _ = time_launches(torch, pf, rig, f.intrinsics, ks, mode, prec, 64, 5)
             extras[f"vga_{mode}_{prec}_Mpx_s"] = round(px_step / (ms * 1e-3) / 1e6, 1)
         del rig

@@ -30,7 +30,8 @@
  *                       (point-to-plane distance over depth: dimensionless)
  *   status    [H][W]    uint8 (optional): bit 0 = invalid window,
  *                       bit 1 = ill-conditioned normal (implicit mode,
- *                       kappa = l3/(l2 - l1) above pf_params.kappa_flag).
+ *                       kappa = l3/(l2 - l1) above pf_params.kappa_flag),
+ *                       bit 2 = solved in FP64 (compensated precision only).
  * A pixel is valid iff its mask byte (if a mask is given) is non-zero and its
  * depth is finite and > 0.  A window is valid iff all k*k pixels lie inside
  * the image and are valid; invalid windows get NaN outputs and status bit 0.
@@ -79,8 +80,12 @@ enum { PF_IMPLICIT = 0, PF_EXPLICIT = 1 };
  *                accurate default.
  *  PF_PREC_FP32: everything in FP32; the throughput reference.  Integral-image
  *                differences lose digits to cancellation, so its errors are
- *                reported, not held to the FP64 oracle's tolerances. */
-enum { PF_PREC_FP64 = 0, PF_PREC_FP32 = 1 };
+ *                reported, not held to the FP64 oracle's tolerances.
+ *  PF_PREC_COMPENSATED: FP32 arithmetic with compensated (two-float, ~48-bit)
+ *                integral-image sums and window moments and an FP32 solve;
+ *                implicit windows whose FP32 eigen-condition kappa exceeds
+ *                pf_params.kappa_fp64 are solved again in FP64 (status bit 2). */
+enum { PF_PREC_FP64 = 0, PF_PREC_FP32 = 1, PF_PREC_COMPENSATED = 2 };
 
 typedef struct {
   int32_t window;     /* k: odd, 3 <= k <= 63, k <= min(H, W) */
@@ -88,6 +93,8 @@ typedef struct {
   int32_t precision;  /* PF_PREC_FP64 or PF_PREC_FP32 */
   int32_t flags;      /* reserved, must be 0 */
   double kappa_flag;  /* implicit mode: set status bit 1 where kappa > this; 0 = never */
+  double kappa_fp64;  /* PF_PREC_COMPENSATED, implicit: FP64 re-solve where the FP32
+                         kappa exceeds this (0 = 100); ignored otherwise */
 } pf_params;
 
 typedef struct pf_plan pf_plan;
@@ -146,7 +153,7 @@ typedef struct {
 /* Enqueue the fits of n frames (Sec. II-C: many fits from one pass over each
  * frame) in as few launches as possible: up to 32 frames per kernel launch,
  * of any sizes and window sizes, each described by its own plan.  All plans
- * must share mode, precision and kappa_flag (else PF_ERR_UNSUPPORTED).  Every
+ * must share mode, precision, kappa_flag and kappa_fp64 (else PF_ERR_UNSUPPORTED).  Every
  * frame is checked on the host as in pf_fit_planes before anything is
  * enqueued; n = 0 is a no-op.  No workspace is needed. */
 pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io, int32_t n,

@@ -20,11 +20,12 @@ STATUS_NAMES = {0: "PF_OK", 1: "PF_ERR_NULL", 2: "PF_ERR_SHAPE", 3: "PF_ERR_WIND
                 4: "PF_ERR_INTRINSICS", 5: "PF_ERR_PITCH", 6: "PF_ERR_ALIGNMENT",
                 7: "PF_ERR_WORKSPACE", 8: "PF_ERR_UNSUPPORTED", 9: "PF_ERR_HIP"}
 MODES = {"implicit": 0, "explicit": 1}
-PRECISIONS = {"fp64": 0, "fp32": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "compensated": 2}
 
 # status byte bits written per pixel
 STATUS_INVALID = 1
 STATUS_ILL_CONDITIONED = 2
+STATUS_FP64_SOLVE = 4
 
 
 class PlanefitError(RuntimeError):
@@ -54,7 +55,7 @@ class _FrameIO(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("window", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("kappa_flag", ctypes.c_double)]
+                ("kappa_flag", ctypes.c_double), ("kappa_fp64", ctypes.c_double)]
 
 
 _lib = None
@@ -119,7 +120,7 @@ class Plan:
 
     def __init__(self, intrinsics, height: int, width: int, window: int,
                  mode: str = "implicit", precision: str = "fp64", kappa_flag: float = 0.0,
-                 flags: int = 0):
+                 flags: int = 0, kappa_fp64: float = 0.0):
         lib = load_library()
         fx, fy, cx, cy = (float(v) for v in intrinsics)
         if mode not in MODES:
@@ -128,7 +129,7 @@ class Plan:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         self._intr = _Intrinsics(fx, fy, cx, cy)
         self._params = _Params(int(window), MODES[mode], PRECISIONS[precision], int(flags),
-                               float(kappa_flag))
+                               float(kappa_flag), float(kappa_fp64))
         h = ctypes.c_void_p()
         _check(lib.pf_plan_create(ctypes.byref(self._intr), int(height), int(width),
                                   ctypes.byref(self._params), ctypes.byref(h)))

@@ -35,6 +35,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "planefit.h"
 
@@ -98,6 +99,7 @@ struct FitArgs {
   double inv_fx, inv_fy;
   double S2, inv_S2, N, inv_N;
   double kappa_flag;
+  double kappa_fp64;  // compensated path: FP64 re-solve above this FP32 kappa
   int vec_store;  // outputs 16-byte aligned, W and tile_w multiples of 4
 };
 
@@ -119,10 +121,12 @@ struct Job {
 // Up to kMaxJobs frames (any sizes and window sizes, one mode and precision)
 // per launch; the whole struct stays under the 4 KiB kernel-argument limit.
 constexpr int kMaxJobs = 32;
+constexpr double kDefaultKappaFp64 = 100.0;
 struct LaunchArgs {
   int32_t n_jobs;
   int32_t n_wg;
   double kappa_flag;
+  double kappa_fp64;
   Job jobs[kMaxJobs];
 };
 static_assert(sizeof(LaunchArgs) <= 4096, "kernel arguments too large");
@@ -202,11 +206,72 @@ __device__ inline float rsq_nr(float x) {
   return y * fmaf(-0.5f * x * y, y, 1.5f);
 }
 
+// ---------------------------------------------------------------------------
+// Two-float ("double-float") arithmetic for the compensated path: a value is
+// the unevaluated sum hi + lo of two FP32 numbers, |lo| <= ulp(hi)/2.  Sums use
+// Knuth's TwoSum and Dekker's FastTwoSum error-free transformations, products
+// use the FMA-based TwoProduct; about 48 significant bits.  Floating-point
+// contraction is switched off inside these functions: fusing the product of
+// TwoProduct into the FastTwoSum that follows would use the exact product where
+// the error term was taken against the rounded one and double-count it.
+// ---------------------------------------------------------------------------
+struct df32 {
+  float hi, lo;
+  df32() = default;
+  __host__ __device__ constexpr df32(float h) : hi(h), lo(0.0f) {}
+  __host__ __device__ constexpr df32(float h, float l) : hi(h), lo(l) {}
+  __host__ __device__ explicit df32(int v) : hi(float(v)), lo(0.0f) {}
+};
+
+__device__ inline df32 two_sum(float a, float b) {
+#pragma clang fp contract(off)
+  const float s = a + b;
+  const float bb = s - a;
+  return df32(s, (a - (s - bb)) + (b - bb));
+}
+__device__ inline df32 fast_two_sum(float a, float b) {
+#pragma clang fp contract(off)
+  const float s = a + b;
+  return df32(s, b - (s - a));
+}
+__device__ inline df32 operator+(df32 a, df32 b) {
+#pragma clang fp contract(off)
+  df32 s = two_sum(a.hi, b.hi);
+  const df32 t = two_sum(a.lo, b.lo);
+  s = fast_two_sum(s.hi, s.lo + t.hi);
+  return fast_two_sum(s.hi, s.lo + t.lo);
+}
+__device__ inline df32 operator-(df32 a) { return df32(-a.hi, -a.lo); }
+__device__ inline df32 operator-(df32 a, df32 b) { return a + (-b); }
+__device__ inline df32& operator+=(df32& a, df32 b) { return a = a + b; }
+__device__ inline df32 operator*(df32 a, df32 b) {
+#pragma clang fp contract(off)
+  const float p = a.hi * b.hi;
+  float e = fmaf(a.hi, b.hi, -p);
+  e = fmaf(a.hi, b.lo, e);
+  e = fmaf(a.lo, b.hi, e);
+  return fast_two_sum(p, e);
+}
+__device__ inline double to_double(df32 a) { return double(a.hi) + double(a.lo); }
+__device__ inline df32 to_df32(double d) {
+  const float h = float(d);
+  return df32(h, float(d - double(h)));
+}
+// 1/z as a two-float: the FMA residual 1 - z r is exact, so r + r (1 - z r)
+// carries the reciprocal to ~2^-46.
+__device__ inline df32 recip(float zf, df32) {
+#pragma clang fp contract(off)
+  const float z = depth_valid(zf) ? zf : 1.0f;
+  const float r = rcp_nr(z);
+  const float e = fmaf(-z, r, 1.0f);
+  return fast_two_sum(r, r * e);
+}
+
 template <typename T>
 __device__ inline void add_sample(float z, int y, T w_ref, int y_ref, Cursor<T>& c) {
   // branch-free: invalid samples contribute exact zeros
   const bool ok = depth_valid(z);
-  const T wh = ok ? recip(z, T(0)) - w_ref : T(0);
+  const T wh = ok ? recip(z, T(0.0f)) - w_ref : T(0.0f);
   c.w += wh;
   c.yw += T(y - y_ref) * wh;
   c.ww += wh * wh;
@@ -264,7 +329,7 @@ __device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22)
   T l = T(0);
   if (c0 > T(0) && c1 > T(0)) {
     l = c0 * rcp_nr(c1);
-    const T tol = sizeof(T) == 8 ? T(1e-13) : T(1e-6);
+    const T tol = sizeof(T) == 8 ? T(1e-13) : T(1e-8);
     for (int it = 0; it < 24; ++it) {
       const T f = ((c2 - l) * l - c1) * l + c0;
       const T fp = (T(2) * c2 - T(3) * l) * l - c1;
@@ -290,36 +355,49 @@ __device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22)
     e.l2 = l3 > T(0) ? pr * rcp_nr(l3) : T(0);
   }
 
-  // eigenvector: largest cross product of two rows of (B - l I)
-  const T a00 = b00 - l, a11 = b11 - l, a22 = b22 - l;
-  // r0 = (a00, b01, b02), r1 = (b01, a11, b12), r2 = (b02, b12, a22)
-  T x0 = b01 * b12 - b02 * a11, y0 = b02 * b01 - a00 * b12, z0 = a00 * a11 - b01 * b01;  // r0 x r1
-  T x1 = b01 * a22 - b02 * b12, y1 = b02 * b02 - a00 * a22, z1 = a00 * b12 - b01 * b02;  // r0 x r2
-  T x2 = a11 * a22 - b12 * b12, y2 = b12 * b02 - b01 * a22, z2 = b01 * b12 - a11 * b02;  // r1 x r2
-  const T n0 = x0 * x0 + y0 * y0 + z0 * z0;
-  const T n1 = x1 * x1 + y1 * y1 + z1 * z1;
-  const T n2 = x2 * x2 + y2 * y2 + z2 * z2;
-  T vx = x0, vy = y0, vz = z0, nn = n0;
-  if (n1 > nn) { vx = x1; vy = y1; vz = z1; nn = n1; }
-  if (n2 > nn) { vx = x2; vy = y2; vz = z2; nn = n2; }
-  if (!(nn > T(0)) || !isfinite(nn)) {
-    // l1 has multiplicity >= 2: any vector orthogonal to the largest row
-    T rx = a00, ry = b01, rz = b02;
-    T rn = rx * rx + ry * ry + rz * rz;
-    const T r1n = b01 * b01 + a11 * a11 + b12 * b12;
-    if (r1n > rn) { rx = b01; ry = a11; rz = b12; rn = r1n; }
-    const T r2n = b02 * b02 + b12 * b12 + a22 * a22;
-    if (r2n > rn) { rx = b02; ry = b12; rz = a22; rn = r2n; }
-    if (rn > T(0)) {
-      // cross with the coordinate axis least aligned with r
-      if (fabs(rx) <= fabs(ry) && fabs(rx) <= fabs(rz)) { vx = T(0); vy = rz; vz = -ry; }
-      else if (fabs(ry) <= fabs(rz)) { vx = -rz; vy = T(0); vz = rx; }
-      else { vx = ry; vy = -rx; vz = T(0); }
-    } else {
-      vx = T(0); vy = T(0); vz = T(1);
+  // eigenvector: largest cross product of two rows of (B - l I); in FP32 the
+  // eigenvalue from the polynomial carries an error ~ eps / f'(l1), so one
+  // Rayleigh-quotient step (l <- v^T B v, then the cross product again) brings
+  // the eigenvector error back from ~eps kappa^2 to ~eps kappa.
+  T vx, vy, vz, nn;
+  const int passes = sizeof(T) == 4 ? 2 : 1;
+  for (int pass = 0; pass < passes; ++pass) {
+    if (pass == 1) {
+      const T ux = vx * rsq_nr(nn), uy = vy * rsq_nr(nn), uz = vz * rsq_nr(nn);
+      l = ux * (b00 * ux + b01 * uy + b02 * uz) + uy * (b01 * ux + b11 * uy + b12 * uz) +
+          uz * (b02 * ux + b12 * uy + b22 * uz);
     }
-    nn = vx * vx + vy * vy + vz * vz;
-    e.degenerate = true;
+    const T a00 = b00 - l, a11 = b11 - l, a22 = b22 - l;
+    // r0 = (a00, b01, b02), r1 = (b01, a11, b12), r2 = (b02, b12, a22)
+    const T x0 = b01 * b12 - b02 * a11, y0 = b02 * b01 - a00 * b12, z0 = a00 * a11 - b01 * b01;
+    const T x1 = b01 * a22 - b02 * b12, y1 = b02 * b02 - a00 * a22, z1 = a00 * b12 - b01 * b02;
+    const T x2 = a11 * a22 - b12 * b12, y2 = b12 * b02 - b01 * a22, z2 = b01 * b12 - a11 * b02;
+    const T n0 = x0 * x0 + y0 * y0 + z0 * z0;
+    const T n1 = x1 * x1 + y1 * y1 + z1 * z1;
+    const T n2 = x2 * x2 + y2 * y2 + z2 * z2;
+    vx = x0; vy = y0; vz = z0; nn = n0;
+    if (n1 > nn) { vx = x1; vy = y1; vz = z1; nn = n1; }
+    if (n2 > nn) { vx = x2; vy = y2; vz = z2; nn = n2; }
+    if (!(nn > T(0)) || !isfinite(nn)) {
+      // l1 has multiplicity >= 2: any vector orthogonal to the largest row
+      T rx = a00, ry = b01, rz = b02;
+      T rn = rx * rx + ry * ry + rz * rz;
+      const T r1n = b01 * b01 + a11 * a11 + b12 * b12;
+      if (r1n > rn) { rx = b01; ry = a11; rz = b12; rn = r1n; }
+      const T r2n = b02 * b02 + b12 * b12 + a22 * a22;
+      if (r2n > rn) { rx = b02; ry = b12; rz = a22; rn = r2n; }
+      if (rn > T(0)) {
+        // cross with the coordinate axis least aligned with r
+        if (fabs(rx) <= fabs(ry) && fabs(rx) <= fabs(rz)) { vx = T(0); vy = rz; vz = -ry; }
+        else if (fabs(ry) <= fabs(rz)) { vx = -rz; vy = T(0); vz = rx; }
+        else { vx = ry; vy = -rx; vz = T(0); }
+      } else {
+        vx = T(0); vy = T(0); vz = T(1);
+      }
+      nn = vx * vx + vy * vy + vz * vz;
+      e.degenerate = true;
+      break;
+    }
   }
   const T inv = rsq_nr(nn);
   e.n[0] = vx * inv;
@@ -342,33 +420,87 @@ __device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22)
 struct PixelOut {
   float n0, n1, n2, d, res;
   uint8_t st;
+  float kappa;  // implicit: l3 / (l2 - l1) of the 3x3 (inf when degenerate)
 };
 
-template <typename T, int MODE>
-__device__ inline PixelOut solve_pixel(const FitArgs& a, T B, T Sxw, T Syw, T Q, int cnt,
-                                       T w_ref, int x0, int y0) {
+__device__ inline PixelOut invalid_pixel() {
   PixelOut o;
-  const int N = a.k * a.k;
-  if (cnt != N) {
-    const float nan = __builtin_nanf("");
-    o.n0 = o.n1 = o.n2 = o.d = o.res = nan;
-    o.st = 1;
-    return o;
+  const float nan = __builtin_nanf("");
+  o.n0 = o.n1 = o.n2 = o.d = o.res = nan;
+  o.st = 1;
+  o.kappa = nan;
+  return o;
+}
+
+// Window moments in window-centred coordinates, from which both solves start:
+//   Sxw = sum x' w, Syw = sum y' w, Sw = sum w, Sww = sum w^2,
+//   V = N sum w^2 - (sum w)^2, SSR = V/N - (Sxw^2 + Syw^2)/S2 (explicit residual).
+template <typename S>
+struct Moments {
+  S Sxw, Syw, Sw, Sww, V, SSR;
+};
+
+// Eq. 14 with |(a, b, c)| = 1: eliminating d leaves G = diag(S2, S2, N) - g g^T / Sww
+// over gamma = (n_x/fx, n_y/fy, n . (u_c, v_c, 1)); C = M^T G M is the 3x3 in n.
+template <typename S>
+struct Implicit3 {
+  S c00, c01, c02, c11, c12, c22;  // C
+  S ifx, ify, uc, vc, iS, Sxw, Syw, Sw, iN;
+};
+
+template <typename S>
+__device__ inline Implicit3<S> implicit_matrix(const FitArgs& a, const Moments<S>& m, S uc, S vc) {
+  Implicit3<S> c;
+  const S S2 = S(a.S2);
+  const S iS = rcp_nr(m.Sww);
+  const S g11 = S2 - m.Sxw * m.Sxw * iS, g22 = S2 - m.Syw * m.Syw * iS;
+  const S g12 = -m.Sxw * m.Syw * iS, g13 = -m.Sxw * m.Sw * iS, g23 = -m.Syw * m.Sw * iS;
+  const S g33 = m.V * iS;
+  const S ifx = S(a.inv_fx), ify = S(a.inv_fy);
+  c.c00 = g11 * ifx * ifx + S(2) * g13 * uc * ifx + g33 * uc * uc;
+  c.c01 = g12 * ifx * ify + g13 * vc * ifx + g23 * uc * ify + g33 * uc * vc;
+  c.c02 = g13 * ifx + g33 * uc;
+  c.c11 = g22 * ify * ify + S(2) * g23 * vc * ify + g33 * vc * vc;
+  c.c12 = g23 * ify + g33 * vc;
+  c.c22 = g33;
+  c.ifx = ifx; c.ify = ify; c.uc = uc; c.vc = vc; c.iS = iS;
+  c.Sxw = m.Sxw; c.Syw = m.Syw; c.Sw = m.Sw; c.iN = S(a.inv_N);
+  return c;
+}
+
+// Orientation (d >= 0), offset, residual sqrt(l1 / N), kappa and its status flag
+// from the smallest eigenpair e (computed in E arithmetic) of C (S arithmetic).
+template <typename S, typename E>
+__device__ inline void finish_implicit(const FitArgs& a, const Implicit3<S>& c, const Eig3<E>& e,
+                                       PixelOut& o) {
+  S n0 = S(e.n[0]), n1 = S(e.n[1]), n2 = S(e.n[2]);
+  const S gp = n0 * c.ifx, gq = n1 * c.ify, gt = n0 * c.uc + n1 * c.vc + n2;
+  S d = -(gp * c.Sxw + gq * c.Syw + gt * c.Sw) * c.iS;
+  if (d < S(0)) {
+    d = -d; n0 = -n0; n1 = -n1; n2 = -n2;
   }
-  const T Nt = T(a.N), iN = T(a.inv_N), S2 = T(a.S2), iS2 = T(a.inv_S2);
-  const T fx = T(a.fx), fy = T(a.fy);
-  const T uc = (T(x0) - T(a.cx)) * T(a.inv_fx);
-  const T vc = (T(y0) - T(a.cy)) * T(a.inv_fy);
-  const T V = Nt * Q - B * B;                      // N sum (w - mean w)^2, reference-free
-  const T Sw = Nt * w_ref + B;                     // sum w
-  const T Sww = Q + w_ref * (T(2) * B + Nt * w_ref);  // sum w^2
+  o.n0 = float(n0);
+  o.n1 = float(n1);
+  o.n2 = float(n2);
+  o.d = float(d);
+  o.res = sqrtf(float(fmax(S(e.l1), S(0)) * c.iN));
+  const E gap = e.l2 - e.l1;
+  o.kappa = (e.degenerate || !(gap > E(0))) ? __builtin_inff() : float(e.l3 / gap);
+  if (a.kappa_flag > 0.0 && !(o.kappa <= float(a.kappa_flag))) o.st |= 2;
+}
+
+template <typename S, int MODE>
+__device__ inline PixelOut solve_moments(const FitArgs& a, const Moments<S>& m, int x0, int y0) {
+  PixelOut o;
   o.st = 0;
+  o.kappa = 0.0f;
+  const S iN = S(a.inv_N), S2 = S(a.S2), iS2 = S(a.inv_S2);
+  const S uc = (S(x0) - S(a.cx)) * S(a.inv_fx);
+  const S vc = (S(y0) - S(a.cy)) * S(a.inv_fy);
   if (MODE == PF_EXPLICIT) {
-    // Eq. 15 in centred regressors (x', y', 1): a' = Sxw/S2, b' = Syw/S2, c' = Sw/N.
-    // The cancellation-prone differences (window sums, SSR) are formed in T; the
-    // closed-form solve from them needs only single precision.
-    const T ssr_t = V * iN - (Sxw * Sxw + Syw * Syw) * iS2;  // sum (w - fit)^2
-    const float ap = float(Sxw * iS2), bp = float(Syw * iS2), cp = float(Sw * iN);
+    // Eq. 15 in centred regressors (x', y', 1): a' = Sxw/S2, b' = Syw/S2, c' = Sw/N;
+    // with the cancellation-prone differences already formed, single precision suffices.
+    const float ap = float(m.Sxw * iS2), bp = float(m.Syw * iS2), cp = float(m.Sw * iN);
     const float aa = float(a.fx) * ap, bb = float(a.fy) * bp;
     const float cc = cp - aa * float(uc) - bb * float(vc);
     const float inv = rsq_nr(aa * aa + bb * bb + cc * cc);
@@ -376,38 +508,68 @@ __device__ inline PixelOut solve_pixel(const FitArgs& a, T B, T Sxw, T Syw, T Q,
     o.n1 = -bb * inv;
     o.n2 = -cc * inv;
     o.d = inv;
-    o.res = inv * sqrtf(fmaxf(float(ssr_t), 0.0f) * float(a.inv_N));
+    o.res = inv * sqrtf(fmaxf(float(m.SSR), 0.0f) * float(a.inv_N));
   } else {
-    // Eq. 14 with |(a, b, c)| = 1: eliminating d leaves G = diag(S2, S2, N) - g g^T / Sww
-    // over gamma = (n_x/fx, n_y/fy, n . (u_c, v_c, 1)); C = M^T G M is the 3x3 in n.
-    const T iS = rcp_nr(Sww);
-    const T g11 = S2 - Sxw * Sxw * iS, g22 = S2 - Syw * Syw * iS;
-    const T g12 = -Sxw * Syw * iS, g13 = -Sxw * Sw * iS, g23 = -Syw * Sw * iS;
-    const T g33 = V * iS;
-    const T ifx = T(a.inv_fx), ify = T(a.inv_fy);
-    const T c00 = g11 * ifx * ifx + T(2) * g13 * uc * ifx + g33 * uc * uc;
-    const T c01 = g12 * ifx * ify + g13 * vc * ifx + g23 * uc * ify + g33 * uc * vc;
-    const T c02 = g13 * ifx + g33 * uc;
-    const T c11 = g22 * ify * ify + T(2) * g23 * vc * ify + g33 * vc * vc;
-    const T c12 = g23 * ify + g33 * vc;
-    const T c22 = g33;
-    Eig3<T> e = smallest_eig<T>(c00, c01, c02, c11, c12, c22);
-    T n0 = e.n[0], n1 = e.n[1], n2 = e.n[2];
-    const T gp = n0 * ifx, gq = n1 * ify, gt = n0 * uc + n1 * vc + n2;
-    T d = -(gp * Sxw + gq * Syw + gt * Sw) * iS;
-    if (d < T(0)) {
-      d = -d; n0 = -n0; n1 = -n1; n2 = -n2;
-    }
-    o.n0 = float(n0);
-    o.n1 = float(n1);
-    o.n2 = float(n2);
-    o.d = float(d);
-    o.res = sqrtf(float(fmax(e.l1, T(0)) * iN));
-    if (a.kappa_flag > 0.0) {
-      const T gap = e.l2 - e.l1;
-      const bool ill = e.degenerate || !(gap > T(0)) || e.l3 > T(a.kappa_flag) * gap;
-      if (ill) o.st |= 2;
-    }
+    const Implicit3<S> c = implicit_matrix<S>(a, m, uc, vc);
+    finish_implicit<S, S>(a, c, smallest_eig<S>(c.c00, c.c01, c.c02, c.c11, c.c12, c.c22), o);
+  }
+  return o;
+}
+
+// Per-pixel solve from the window sums (FP32 or FP64 arithmetic throughout).
+//   B  = sum (w - w_ref)                 Sxw = sum (x - x_c)(w - w_ref)
+//   Syw = sum (y - y_c)(w - w_ref)       Q  = sum (w - w_ref)^2
+// where x_c, y_c are the window centre's column and row; w = 1/Z.
+template <typename T, int MODE>
+__device__ inline PixelOut solve_pixel(const FitArgs& a, T B, T Sxw, T Syw, T Q, int cnt,
+                                       T w_ref, int x0, int y0) {
+  if (cnt != a.k * a.k) return invalid_pixel();
+  const T Nt = T(a.N);
+  Moments<T> m;
+  m.Sxw = Sxw;
+  m.Syw = Syw;
+  m.V = Nt * Q - B * B;                          // N sum (w - mean w)^2, reference-free
+  m.Sw = Nt * w_ref + B;                          // sum w
+  m.Sww = Q + w_ref * (T(2) * B + Nt * w_ref);    // sum w^2
+  m.SSR = m.V * T(a.inv_N) - (Sxw * Sxw + Syw * Syw) * T(a.inv_S2);
+  return solve_moments<T, MODE>(a, m, x0, y0);
+}
+
+// Compensated path: moments formed in two-float arithmetic, solved in FP32;
+// an implicit window whose FP32 eigen-condition kappa exceeds the plan's
+// threshold is solved again in FP64 from the same two-float moments (status
+// bit 2 records it).
+template <int MODE>
+__device__ inline PixelOut solve_pixel_df(const FitArgs& a, df32 B, df32 Sxw, df32 Syw, df32 Q,
+                                          int cnt, df32 w_ref, int x0, int y0) {
+  if (cnt != a.k * a.k) return invalid_pixel();
+  const df32 Nt(float(a.k * a.k));
+  const df32 V = Nt * Q - B * B;
+  const df32 Sw = Nt * w_ref + B;
+  const df32 Sww = Q + w_ref * (B + B + Nt * w_ref);
+  const df32 iS2 = to_df32(a.inv_S2), iN = to_df32(a.inv_N);
+  const df32 SSR = V * iN - (Sxw * Sxw + Syw * Syw) * iS2;
+  if (MODE == PF_EXPLICIT) {
+    Moments<float> mf = {Sxw.hi, Syw.hi, Sw.hi, Sww.hi, V.hi, SSR.hi};
+    return solve_moments<float, MODE>(a, mf, x0, y0);
+  }
+  // Implicit: the 3x3 is formed from the two-float moments in FP64 (C = M^T G M
+  // cancels terms up to ~f^2 times larger than its entries), its smallest
+  // eigenpair is found in FP32, and windows whose FP32 kappa exceeds the
+  // threshold are solved again in FP64.
+  const Moments<double> md = {to_double(Sxw), to_double(Syw), to_double(Sw), to_double(Sww),
+                              to_double(V), to_double(SSR)};
+  const double uc = (double(x0) - a.cx) * a.inv_fx, vc = (double(y0) - a.cy) * a.inv_fy;
+  const Implicit3<double> c = implicit_matrix<double>(a, md, uc, vc);
+  PixelOut o;
+  o.st = 0;
+  const Eig3<float> ef = smallest_eig<float>(float(c.c00), float(c.c01), float(c.c02),
+                                             float(c.c11), float(c.c12), float(c.c22));
+  finish_implicit<double, float>(a, c, ef, o);
+  if (!(o.kappa <= float(a.kappa_fp64))) {
+    o.st = 4;
+    finish_implicit<double, double>(a, c, smallest_eig<double>(c.c00, c.c01, c.c02, c.c11,
+                                                               c.c12, c.c22), o);
   }
   return o;
 }
@@ -457,6 +619,7 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
   a.S2 = a.N * (a.N - 1.0) / 12.0;
   a.inv_S2 = 1.0 / a.S2;
   a.kappa_flag = la.kappa_flag;
+  a.kappa_fp64 = la.kappa_fp64;
   a.vec_store = job.vec_store;
 
   __shared__ T sw[TL::rows * kPitch];
@@ -500,7 +663,11 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
       wc += red[2 * i + 1];
     }
   }
-  const T w_ref = wc > 0.0 ? T(ws / wc) : T(0);
+  T w_ref;
+  if constexpr (std::is_same<T, df32>::value)
+    w_ref = wc > 0.0 ? to_df32(ws / wc) : df32(0.0f);
+  else
+    w_ref = wc > 0.0 ? T(ws / wc) : T(0);
 
   Cursor<T> lead, lag;
   lead.clear();
@@ -601,7 +768,11 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
         const int cnt = hn - gn;
         const T Sxw = Fx - T(q) * B;
         const T Syw = Fy - T(y0 - y_ref) * B;
-        const PixelOut po = solve_pixel<T, MODE>(a, B, Sxw, Syw, Q, cnt, w_ref, ox0 + o, y0);
+        PixelOut po;
+        if constexpr (std::is_same<T, df32>::value)
+          po = solve_pixel_df<MODE>(a, B, Sxw, Syw, Q, cnt, w_ref, ox0 + o, y0);
+        else
+          po = solve_pixel<T, MODE>(a, B, Sxw, Syw, Q, cnt, w_ref, ox0 + o, y0);
         {
           const int l = lds_index<MODE>(o);
           const T v = rw[l];
@@ -741,8 +912,10 @@ pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t widt
   const int k = params->window;
   if (k < 3 || k > kMaxWindow || (k % 2) == 0 || k > height || k > width) return PF_ERR_WINDOW;
   if ((params->mode != PF_IMPLICIT && params->mode != PF_EXPLICIT) ||
-      (params->precision != PF_PREC_FP64 && params->precision != PF_PREC_FP32) ||
-      params->flags != 0 || !(params->kappa_flag >= 0.0) || !std::isfinite(params->kappa_flag))
+      (params->precision != PF_PREC_FP64 && params->precision != PF_PREC_FP32 &&
+       params->precision != PF_PREC_COMPENSATED) ||
+      params->flags != 0 || !(params->kappa_flag >= 0.0) || !std::isfinite(params->kappa_flag) ||
+      !(params->kappa_fp64 >= 0.0) || !std::isfinite(params->kappa_fp64))
     return PF_ERR_UNSUPPORTED;
   pf_plan* p = new (std::nothrow) pf_plan;
   if (!p) return PF_ERR_UNSUPPORTED;
@@ -818,11 +991,12 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
       return PF_ERR_ALIGNMENT;
     if (p->params.mode != plans[0]->params.mode ||
         p->params.precision != plans[0]->params.precision ||
-        p->params.kappa_flag != plans[0]->params.kappa_flag)
+        p->params.kappa_flag != plans[0]->params.kappa_flag ||
+        p->params.kappa_fp64 != plans[0]->params.kappa_fp64)
       return PF_ERR_UNSUPPORTED;
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const bool fp64 = plans[0]->params.precision == PF_PREC_FP64;
+  const int prec = plans[0]->params.precision;
   const bool expl = plans[0]->params.mode == PF_EXPLICIT;
   for (int32_t first = 0; first < n; first += kMaxJobs) {
     const int32_t cnt = std::min<int32_t>(kMaxJobs, n - first);
@@ -830,6 +1004,8 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
     std::memset(&la, 0, sizeof(la));
     la.n_jobs = cnt;
     la.kappa_flag = plans[first]->params.kappa_flag;
+    la.kappa_fp64 = plans[first]->params.kappa_fp64 > 0.0 ? plans[first]->params.kappa_fp64
+                                                           : kDefaultKappaFp64;
     bool has_mask = false;
     int32_t wg = 0;
     for (int32_t j = 0; j < cnt; ++j) {
@@ -866,15 +1042,21 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
     const dim3 block(kBlock);
 #define PF_LAUNCH(T, M, K) \
   hipLaunchKernelGGL((fit_planes_fused<T, M, K>), grid, block, 0, s, la)
-    if (fp64 && expl) {
-      if (has_mask) PF_LAUNCH(double, PF_EXPLICIT, true); else PF_LAUNCH(double, PF_EXPLICIT, false);
-    } else if (fp64) {
-      if (has_mask) PF_LAUNCH(double, PF_IMPLICIT, true); else PF_LAUNCH(double, PF_IMPLICIT, false);
-    } else if (expl) {
-      if (has_mask) PF_LAUNCH(float, PF_EXPLICIT, true); else PF_LAUNCH(float, PF_EXPLICIT, false);
-    } else {
-      if (has_mask) PF_LAUNCH(float, PF_IMPLICIT, true); else PF_LAUNCH(float, PF_IMPLICIT, false);
-    }
+#define PF_LAUNCH_MODES(T)                                                     \
+  do {                                                                         \
+    if (expl) {                                                                \
+      if (has_mask) PF_LAUNCH(T, PF_EXPLICIT, true); else PF_LAUNCH(T, PF_EXPLICIT, false); \
+    } else {                                                                   \
+      if (has_mask) PF_LAUNCH(T, PF_IMPLICIT, true); else PF_LAUNCH(T, PF_IMPLICIT, false); \
+    }                                                                          \
+  } while (0)
+    if (prec == PF_PREC_FP64)
+      PF_LAUNCH_MODES(double);
+    else if (prec == PF_PREC_FP32)
+      PF_LAUNCH_MODES(float);
+    else
+      PF_LAUNCH_MODES(df32);
+#undef PF_LAUNCH_MODES
 #undef PF_LAUNCH
     const hipError_t err = hipGetLastError();
     if (err != hipSuccess) {

@@ -36,7 +36,7 @@ def _create(intr=(525.0, 525.0, 319.5, 239.5), H=480, W=640, k=5, mode=0, prec=0
     lib = pf.load_library()
     h = ctypes.c_void_p()
     code = lib.pf_plan_create(ctypes.byref(_Intrinsics(*intr)), H, W,
-                              ctypes.byref(_Params(k, mode, prec, flags, kappa)), ctypes.byref(h))
+                              ctypes.byref(_Params(k, mode, prec, flags, kappa, 0.0)), ctypes.byref(h))
     return code, h
 
 
@@ -46,6 +46,7 @@ def _create(intr=(525.0, 525.0, 319.5, 239.5), H=480, W=640, k=5, mode=0, prec=0
     (dict(intr=(0.0, 525.0, 1.0, 1.0)), 4), (dict(intr=(525.0, float("nan"), 1.0, 1.0)), 4),
     (dict(intr=(525.0, 525.0, float("inf"), 1.0)), 4),
     (dict(mode=2), 8), (dict(prec=7), 8), (dict(flags=1), 8), (dict(kappa=-1.0), 8),
+    (dict(prec=2), 0),
     (dict(), 0), (dict(H=63, W=63, k=63), 0), (dict(mode=1, prec=1, kappa=1e6), 0),
 ])
 def test_plan_validation(kw, code):
@@ -61,7 +62,7 @@ def test_plan_validation(kw, code):
 def test_plan_create_null_arguments():
     lib = pf.load_library()
     h = ctypes.c_void_p()
-    assert lib.pf_plan_create(None, 10, 10, ctypes.byref(_Params(3, 0, 0, 0, 0.0)),
+    assert lib.pf_plan_create(None, 10, 10, ctypes.byref(_Params(3, 0, 0, 0, 0.0, 0.0)),
                               ctypes.byref(h)) == 1
     assert lib.pf_plan_create(ctypes.byref(_Intrinsics(1, 1, 1, 1)), 10, 10, None,
                               ctypes.byref(h)) == 1

@@ -185,6 +185,69 @@ def batch_measure(torch, pf, np, frames_for):
             "graph_Mpx_s": round(px / (graph * 1e-3) / 1e6, 1)}
 
 
+def diff_measure(torch, pf, np, frames_for, diff_loss_inputs):
+    """The differentiation workload: 8 frames of 640x480, k = 9, implicit FP64.
+    One step = the forward fits of the 8 frames (one batched launch) and the
+    backward pass of each frame for L = sum W (1 - n . t) + 0.1 r (two launches
+    per frame), replayed from a captured HIP graph; the backward alone is timed
+    the same way."""
+    frames = frames_for("diff_8x640x480")
+    k = frames[0].window
+    intr = frames[0].intrinsics
+    H, W = frames[0].depth.shape
+    depth = [torch.from_numpy(f.depth).cuda() for f in frames]
+    outs = [(torch.empty((3, H, W), device="cuda"), torch.empty((H, W), device="cuda"),
+             torch.empty((H, W), device="cuda"), torch.empty((H, W), dtype=torch.uint8, device="cuda"))
+            for _ in frames]
+    ups = []
+    for i in range(len(frames)):
+        w, t = diff_loss_inputs(H, W, 6000 + i)
+        wt = torch.from_numpy(w.astype(np.float32)).cuda()
+        tt = torch.from_numpy(t.astype(np.float32)).cuda()
+        ups.append(((-wt[None] * tt).contiguous(), (0.1 * wt).contiguous()))
+    grads = [torch.empty((H, W), device="cuda") for _ in frames]
+    pf.get_plan(intr, H, W, k, "implicit", "fp64")
+
+    def fwd():
+        pf.fit_planes_batch(depth, intr, k, mode="implicit", outs=outs)
+
+    def bwd():
+        for i in range(len(frames)):
+            pf.fit_planes_backward(depth[i], intr, k, ups[i][0], None, ups[i][1], out=grads[i])
+
+    def both():
+        fwd()
+        bwd()
+
+    res = {"frames": len(frames), "pixels": len(frames) * H * W, "k": k, "mode": "implicit",
+           "precision": "fp64"}
+    for name, fn in (("fwd_bwd", both), ("bwd", bwd)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                fn()
+        torch.cuda.current_stream().wait_stream(side)
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        n = 30
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(n):
+            g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / n
+        res[f"{name}_ms"] = round(ms, 4)
+        res[f"{name}_Mpx_s"] = round(res["pixels"] / (ms * 1e-3) / 1e6, 1)
+    return res
+
+
 def cpu_baseline(frame, ks, mode, budget_s):
     """The FP64 oracle on the host: random sample of window centres, growing until
     about budget_s seconds of work; returns Mpixel/s and what was sampled."""
@@ -224,7 +287,7 @@ def main():
     import numpy as np
     import torch
     import paper_2103_06644_amd as pf
-    from depthsynth import frames_for
+    from depthsynth import diff_loss_inputs, frames_for
 
     pf.load_library()
     if args.copy_probe:
@@ -282,6 +345,7 @@ def main():
         del rig_hd
         torch.cuda.empty_cache()
         extras["batch_mixed_64"] = batch_measure(torch, pf, np, frames_for)
+        extras["diff_8x640x480"] = diff_measure(torch, pf, np, frames_for, diff_loss_inputs)
         out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(f, ks, "implicit", args.cpu_seconds)

@@ -159,6 +159,33 @@ typedef struct {
 pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io, int32_t n,
                               void* stream);
 
+/* Bytes of device workspace pf_fit_planes_backward needs: 32 * H * W (the four
+ * per-window moment gradients in FP64). */
+size_t pf_backward_workspace_bytes(const pf_plan* plan);
+
+/* Backward pass of pf_fit_planes for one frame: the gradient of a scalar loss
+ * with respect to the depth image, given the loss's gradients with respect to
+ * the outputs.  The solve of Eq. 14-16 is differentiated per window (FP64,
+ * whatever the plan's precision; for the implicit fit through the derivative of
+ * the smallest eigenpair, d n = -(C - l1 I)^+ dC n), and the window sums of the
+ * integral images (Sec. II-C) are differentiated by the same box-sum sweep run
+ * over the per-window gradients; finally w = 1/Z is chained to Z.
+ *   depth, mask            as given to pf_fit_planes
+ *   grad_normals           device float[3][H][W] or NULL (zero)
+ *   grad_offsets           device float[H][W] or NULL (zero)
+ *   grad_residuals         device float[H][W] or NULL (zero)
+ *   grad_depth             device float[H][W] (written, dense pitch W)
+ *   workspace              device buffer >= pf_backward_workspace_bytes(plan),
+ *                          8-byte aligned; contents undefined afterwards
+ * Invalid windows and windows whose normal is not differentiable (a repeated
+ * smallest eigenvalue) contribute nothing; invalid pixels get 0.  Upstream
+ * gradients at invalid windows are ignored (their outputs are NaN). */
+pf_status pf_fit_planes_backward(const pf_plan* plan, const float* depth, int64_t depth_pitch,
+                                 const uint8_t* mask, int64_t mask_pitch,
+                                 const float* grad_normals, const float* grad_offsets,
+                                 const float* grad_residuals, float* grad_depth, void* workspace,
+                                 size_t workspace_bytes, void* stream);
+
 /* Static description of a status code. */
 const char* pf_status_string(pf_status s);
 

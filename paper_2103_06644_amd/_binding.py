@@ -63,6 +63,7 @@ _lib_lock = threading.Lock()
 
 EXPORTS = ("pf_plan_create", "pf_plan_destroy", "pf_plan_workspace_bytes",
            "pf_plan_camera_moments", "pf_fit_planes", "pf_fit_planes_batch",
+           "pf_backward_workspace_bytes", "pf_fit_planes_backward",
            "pf_status_string", "pf_last_hip_error")
 
 
@@ -92,6 +93,11 @@ def load_library(path: str | None = None):
         lib.pf_fit_planes.restype = i32
         lib.pf_fit_planes_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_FrameIO), i32, vp]
         lib.pf_fit_planes_batch.restype = i32
+        lib.pf_backward_workspace_bytes.argtypes = [vp]
+        lib.pf_backward_workspace_bytes.restype = ctypes.c_size_t
+        lib.pf_fit_planes_backward.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp,
+                                               ctypes.c_size_t, vp]
+        lib.pf_fit_planes_backward.restype = i32
         lib.pf_status_string.argtypes = [i32]
         lib.pf_status_string.restype = ctypes.c_char_p
         lib.pf_last_hip_error.argtypes = []
@@ -146,6 +152,10 @@ class Plan:
     @property
     def workspace_bytes(self) -> int:
         return int(self._lib.pf_plan_workspace_bytes(self._h))
+
+    @property
+    def backward_workspace_bytes(self) -> int:
+        return int(self._lib.pf_backward_workspace_bytes(self._h))
 
     def camera_moments(self, x0: int, y0: int):
         out = (ctypes.c_double * 6)()
@@ -325,3 +335,86 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
         code = lib.pf_fit_planes_batch(handles, ios, n, _stream_handle(torch, dev, stream))
     _check(code)
     return results
+
+
+def fit_planes_backward(depth, intrinsics, window: int, grad_normals=None, grad_offsets=None,
+                        grad_residuals=None, valid_mask=None, *, mode: str = "implicit",
+                        out=None, stream=None):
+    """Gradient of a scalar loss with respect to the depth image, given the
+    loss's gradients with respect to the outputs of fit_planes (each optional,
+    float32 [3,H,W] / [H,W] / [H,W] on depth's device).  Differentiated in FP64
+    on the GPU; returns dL/dZ as float32 [H, W]."""
+    import torch
+    _check_depth(torch, depth)
+    H, W = depth.shape
+    dev = depth.device
+    plan = get_plan(intrinsics, H, W, window, mode, "fp64", 0.0)
+    mptr, mpitch = _mask_arg(torch, valid_mask, depth)
+    ptrs = []
+    for g, shp in ((grad_normals, (3, H, W)), (grad_offsets, (H, W)), (grad_residuals, (H, W))):
+        if g is None:
+            ptrs.append(None)
+            continue
+        if (tuple(g.shape) != shp or g.dtype != torch.float32 or not g.is_contiguous()
+                or g.device != dev):
+            raise ValueError(f"output gradients must be contiguous float32 {shp} on depth's device")
+        ptrs.append(ctypes.c_void_p(g.data_ptr()))
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=dev)
+    elif (tuple(out.shape) != (H, W) or out.dtype != torch.float32 or not out.is_contiguous()
+          or out.device != dev):
+        raise ValueError("out must be a contiguous float32 [H, W] tensor on depth's device")
+    ws = plan.backward_workspace_bytes
+    work = torch.empty(ws, dtype=torch.uint8, device=dev)
+    with _on_device(torch, dev):
+        code = plan._lib.pf_fit_planes_backward(
+            plan.handle, ctypes.c_void_p(depth.data_ptr()), depth.stride(0),
+            ctypes.c_void_p(mptr) if mptr else None, mpitch, ptrs[0], ptrs[1], ptrs[2],
+            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(work.data_ptr()), ws,
+            _stream_handle(torch, dev, stream))
+    _check(code)
+    return out
+
+
+def _autograd_function():
+    import torch
+
+    class FitPlanesFunction(torch.autograd.Function):
+        """fit_planes as a differentiable op: forward in the requested
+        precision, backward in FP64 through pf_fit_planes_backward."""
+
+        @staticmethod
+        def forward(ctx, depth, intrinsics, window, valid_mask, mode, precision):
+            n, d, r, st = fit_planes(depth, intrinsics, window, valid_mask, mode=mode,
+                                     precision=precision)
+            ctx.save_for_backward(depth, valid_mask if valid_mask is not None else depth.new_empty(0))
+            ctx.has_mask = valid_mask is not None
+            ctx.cfg = (tuple(intrinsics), window, mode)
+            ctx.mark_non_differentiable(st)
+            return n, d, r, st
+
+        @staticmethod
+        def backward(ctx, gn, gd, gr, gst):
+            depth, mask = ctx.saved_tensors
+            intr, k, mode = ctx.cfg
+            prep = lambda g: None if g is None else g.contiguous()
+            dz = fit_planes_backward(depth, intr, k, prep(gn), prep(gd), prep(gr),
+                                     mask if ctx.has_mask else None, mode=mode)
+            return dz, None, None, None, None, None
+
+    return FitPlanesFunction
+
+
+_fn_cache = []
+
+
+def fit_planes_differentiable(depth, intrinsics, window: int, valid_mask=None, *,
+                              mode: str = "implicit", precision: str = "fp64"):
+    """fit_planes with autograd support with respect to `depth`.  Gradients at
+    invalid windows are ignored (their outputs are NaN: mask them out of the
+    loss, e.g. with torch.where on the status), as are gradients at windows
+    whose smallest eigenvalue is repeated."""
+    if not _fn_cache:
+        _fn_cache.append(_autograd_function())
+    return _fn_cache[0].apply(depth, tuple(float(v) for v in intrinsics), int(window),
+                              valid_mask, mode, precision)

@@ -101,6 +101,7 @@ struct FitArgs {
   double kappa_flag;
   double kappa_fp64;  // compensated path: FP64 re-solve above this FP32 kappa
   int vec_store;  // outputs 16-byte aligned, W and tile_w multiples of 4
+  double* gws;    // backward: per-window moment gradients [4][H][W]
 };
 
 // One frame of a launch, passed by value in the kernel arguments.
@@ -127,6 +128,7 @@ struct LaunchArgs {
   int32_t n_wg;
   double kappa_flag;
   double kappa_fp64;
+  double* gws;  // backward pass only (single job): moment-gradient workspace
   Job jobs[kMaxJobs];
 };
 static_assert(sizeof(LaunchArgs) <= 4096, "kernel arguments too large");
@@ -575,6 +577,117 @@ __device__ inline PixelOut solve_pixel_df(const FitArgs& a, df32 B, df32 Sxw, df
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint of the per-pixel solve (FP64).  Given the upstream gradients of one
+// window's outputs (normal, offset, residual) it returns the gradients of the
+// four window moments the fit depends on,
+//   Sw = sum w, Sx = sum x' w, Sy = sum y' w, Sww = sum w^2,
+// which the box-sum adjoint then spreads back over the window's pixels.
+// ---------------------------------------------------------------------------
+struct MomentGrad {
+  double Sw, Sx, Sy, Sww;
+};
+
+__device__ inline MomentGrad explicit_adjoint(const FitArgs& a, double Sx, double Sy, double Sw,
+                                              double V, double uc, double vc, double gnx,
+                                              double gny, double gnz, double gd, double gr) {
+  // forward: alpha = (fx Sx/S2, fy Sy/S2, Sw/N - ...), n = -alpha/|alpha|, d = 1/|alpha|,
+  // r = d sqrt(SSR/N) with SSR = Sww - Sw^2/N - (Sx^2 + Sy^2)/S2
+  const double N = a.N, S2 = a.S2;
+  const double ax = a.fx * Sx / S2, ay = a.fy * Sy / S2;
+  const double az = Sw / N - ax * uc - ay * vc;
+  const double rho = sqrt(ax * ax + ay * ay + az * az);
+  const double nx = -ax / rho, ny = -ay / rho, nz = -az / rho, d = 1.0 / rho;
+  const double ssr = fmax(V / N - (Sx * Sx + Sy * Sy) / S2, 0.0);
+  const double sr = sqrt(ssr / N);
+  const double gdt = gd + gr * sr;  // d enters r as a factor
+  // dn = -(I - n n^T) dalpha / rho, dd = -alpha^T dalpha / rho^3 = n^T dalpha / rho^2
+  const double ng = nx * gnx + ny * gny + nz * gnz;
+  const double gax = -(gnx - nx * ng) / rho + gdt * nx / (rho * rho);
+  const double gay = -(gny - ny * ng) / rho + gdt * ny / (rho * rho);
+  const double gaz = -(gnz - nz * ng) / rho + gdt * nz / (rho * rho);
+  const double gssr = sr > 0.0 ? gr * d / (2.0 * sr * N) : 0.0;
+  MomentGrad g;
+  g.Sx = a.fx * (gax - uc * gaz) / S2 - 2.0 * Sx * gssr / S2;
+  g.Sy = a.fy * (gay - vc * gaz) / S2 - 2.0 * Sy * gssr / S2;
+  g.Sw = gaz / N - 2.0 * Sw * gssr / N;
+  g.Sww = gssr;
+  return g;
+}
+
+__device__ inline MomentGrad implicit_adjoint(const FitArgs& a, const Moments<double>& m,
+                                              double uc, double vc, double gnx, double gny,
+                                              double gnz, double gd, double gr) {
+  MomentGrad g = {0.0, 0.0, 0.0, 0.0};
+  const Implicit3<double> c = implicit_matrix<double>(a, m, uc, vc);
+  const Eig3<double> e = smallest_eig<double>(c.c00, c.c01, c.c02, c.c11, c.c12, c.c22);
+  if (e.degenerate || !(e.l2 > e.l1)) return g;  // the normal is not differentiable here
+  double n0 = e.n[0], n1 = e.n[1], n2 = e.n[2];
+  const double gv[3] = {m.Sxw, m.Syw, m.Sw};  // g = (Sx, Sy, Sw)
+  double gm0 = n0 * c.ifx, gm1 = n1 * c.ify, gm2 = n0 * uc + n1 * vc + n2;  // gamma = M n
+  double d = -(gm0 * gv[0] + gm1 * gv[1] + gm2 * gv[2]) * c.iS;
+  if (d < 0.0) {
+    d = -d; n0 = -n0; n1 = -n1; n2 = -n2; gm0 = -gm0; gm1 = -gm1; gm2 = -gm2;
+  }
+  const double iS = c.iS, N = a.N;
+  const double r = sqrt(fmax(e.l1, 0.0) / N);
+  // d = -gamma^T g / Sww depends on n through gamma = M n: dd/dn = -M^T g / Sww
+  const double mtg0 = c.ifx * gv[0] + uc * gv[2], mtg1 = c.ify * gv[1] + vc * gv[2];
+  const double mtg2 = gv[2];
+  double bn0 = gnx - gd * mtg0 * iS, bn1 = gny - gd * mtg1 * iS, bn2 = gnz - gd * mtg2 * iS;
+  const double glam = r > 0.0 ? gr / (2.0 * N * r) : 0.0;
+  // dn = -(C - l1 I)^+ dC n: y = (C - l1 I + mu n n^T)^-1 b for b orthogonal to n
+  const double nb = n0 * bn0 + n1 * bn1 + n2 * bn2;
+  bn0 -= n0 * nb; bn1 -= n1 * nb; bn2 -= n2 * nb;
+  const double mu = e.l3 - e.l1;
+  const double a00 = c.c00 - e.l1 + mu * n0 * n0, a01 = c.c01 + mu * n0 * n1;
+  const double a02 = c.c02 + mu * n0 * n2, a11 = c.c11 - e.l1 + mu * n1 * n1;
+  const double a12 = c.c12 + mu * n1 * n2, a22 = c.c22 - e.l1 + mu * n2 * n2;
+  const double k00 = a11 * a22 - a12 * a12, k01 = a02 * a12 - a01 * a22, k02 = a01 * a12 - a02 * a11;
+  const double k11 = a00 * a22 - a02 * a02, k12 = a01 * a02 - a00 * a12, k22 = a00 * a11 - a01 * a01;
+  const double det = a00 * k00 + a01 * k01 + a02 * k02;
+  if (!(fabs(det) > 0.0)) return g;
+  const double idet = 1.0 / det;
+  const double y0 = (k00 * bn0 + k01 * bn1 + k02 * bn2) * idet;
+  const double y1 = (k01 * bn0 + k11 * bn1 + k12 * bn2) * idet;
+  const double y2 = (k02 * bn0 + k12 * bn1 + k22 * bn2) * idet;
+  // dL/dC = glam n n^T - sym(y n^T)
+  const double n[3] = {n0, n1, n2}, y[3] = {y0, y1, y2};
+  double GC[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) GC[i][j] = glam * n[i] * n[j] - 0.5 * (y[i] * n[j] + n[i] * y[j]);
+  // C = M^T G M  ->  dL/dG = M dL/dC M^T, with M = [[1/fx,0,0],[0,1/fy,0],[uc,vc,1]]
+  const double M[3][3] = {{c.ifx, 0.0, 0.0}, {0.0, c.ify, 0.0}, {uc, vc, 1.0}};
+  double T1[3][3], GG[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int t = 0; t < 3; ++t) s += M[i][t] * GC[t][j];
+      T1[i][j] = s;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int t = 0; t < 3; ++t) s += T1[i][t] * M[j][t];
+      GG[i][j] = s;
+    }
+  // G = diag(S2, S2, N) - g g^T / Sww: dL/dg = -2 dL/dG g / Sww, dL/dSww = g^T dL/dG g / Sww^2;
+  // plus the offset's direct terms dd/dg = -gamma / Sww, dd/dSww = -d / Sww
+  const double gm[3] = {gm0, gm1, gm2};
+  double gg[3], qg = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    double s = 0.0;
+    for (int t = 0; t < 3; ++t) s += GG[i][t] * gv[t];
+    gg[i] = -2.0 * s * iS - gd * gm[i] * iS;
+    qg += gv[i] * s;
+  }
+  g.Sx = gg[0];
+  g.Sy = gg[1];
+  g.Sw = gg[2];
+  g.Sww = qg * iS * iS - gd * d * iS;
+  return g;
+}
+
+// ---------------------------------------------------------------------------
 // The fused kernel.  Workgroup = one strip of kBlock input columns (tile_w
 // output columns plus k-1 halo) by one band of tile_h output rows.
 //
@@ -582,7 +695,7 @@ __device__ inline PixelOut solve_pixel_df(const FitArgs& a, df32 B, df32 Sxw, df
 // yb-r .. y0+r and the lag cursor rows yb-r .. y0-r-1, so lead - lag is the
 // column sum over the window rows y0-r .. y0+r.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, bool MASK>
+template <typename T, int MODE, bool MASK, bool BWD = false>
 __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
   using TL = Tiling<MODE>;
   // which job and which of its workgroups (the job table is uniform: scalar loop)
@@ -621,6 +734,7 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
   a.kappa_flag = la.kappa_flag;
   a.kappa_fp64 = la.kappa_fp64;
   a.vec_store = job.vec_store;
+  a.gws = la.gws;
 
   __shared__ T sw[TL::rows * kPitch];
   __shared__ T syw[TL::rows * kPitch];
@@ -784,7 +898,63 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
         }
         return po;
       };
-      if (MODE == PF_IMPLICIT) {
+      if constexpr (BWD) {
+        // backward: per-window moment gradients from the upstream output gradients
+        const int64_t prow = (int64_t)y0 * a.W + ox0;
+#pragma unroll 1
+        for (int q = 0; q < o1 - o0; ++q) {
+          const int o = o0 + q;
+          {
+            const int i = o + a.k - 1;
+            const int l = lds_index<MODE>(i);
+            const T v = rw[l];
+            hw += v;
+            hx += T(i - base) * v;
+            hy += ryw[l];
+            hww += rww[l];
+            hn += rn[l];
+          }
+          const double B = hw - gw, Q = hww - gww;
+          const double Sxw = (hx - gx) - double(q) * B, Syw = (hy - gy) - double(y0 - y_ref) * B;
+          const int cnt = hn - gn;
+          {
+            const int l = lds_index<MODE>(o);
+            const T v = rw[l];
+            gw += v;
+            gx += T(o - base) * v;
+            gy += ryw[l];
+            gww += rww[l];
+            gn += rn[l];
+          }
+          const int x0 = ox0 + o;
+          if (x0 >= a.W) continue;
+          const int64_t pp = prow + o;
+          MomentGrad mg = {0.0, 0.0, 0.0, 0.0};
+          if (cnt == a.k * a.k) {
+            const double uc = (double(x0) - a.cx) * a.inv_fx, vc = (double(y0) - a.cy) * a.inv_fy;
+            const double gnx = a.normals ? a.normals[pp] : 0.0;
+            const double gny = a.normals ? a.normals[a.plane + pp] : 0.0;
+            const double gnz = a.normals ? a.normals[2 * a.plane + pp] : 0.0;
+            const double gd = a.offsets ? a.offsets[pp] : 0.0;
+            const double gr = a.residuals ? a.residuals[pp] : 0.0;
+            Moments<double> m;
+            m.Sxw = Sxw;
+            m.Syw = Syw;
+            m.V = a.N * Q - B * B;
+            m.Sw = a.N * double(w_ref) + B;
+            m.Sww = Q + double(w_ref) * (2.0 * B + a.N * double(w_ref));
+            m.SSR = 0.0;
+            if (MODE == PF_EXPLICIT)
+              mg = explicit_adjoint(a, Sxw, Syw, m.Sw, m.V, uc, vc, gnx, gny, gnz, gd, gr);
+            else
+              mg = implicit_adjoint(a, m, uc, vc, gnx, gny, gnz, gd, gr);
+          }
+          a.gws[pp] = mg.Sw;
+          a.gws[a.plane + pp] = mg.Sx;
+          a.gws[2 * a.plane + pp] = mg.Sy;
+          a.gws[3 * a.plane + pp] = mg.Sww;
+        }
+      } else if (MODE == PF_IMPLICIT) {
         // the eigen-solve is large: keep the loop rolled and store each pixel directly
         const int64_t prow = (int64_t)y0 * a.W + ox0;
 #pragma unroll 1
@@ -855,6 +1025,129 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
           }
         }
       }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward, second sweep: dL/dZ.  Every window sum S(p) = sum_{i in W_p} f_i
+// is adjoint to a box sum over the windows containing pixel i, and for a k x k
+// window those are exactly the windows centred in the k x k neighbourhood of i.
+// So the same two-cursor integral-image sweep, run over the per-window moment
+// gradients instead of the depth integrands, gives
+//   dL/dw_i = sum_p [gSw(p) - (x_p - x_i) gSx(p) - (y_p - y_i) gSy(p) + 2 w_i gSww(p)]
+// and dL/dZ_i = -dL/dw_i / Z_i^2 (0 for invalid pixels).  FP64 throughout.
+// The job's `normals` pointer carries the float dL/dZ output [H][W].
+// ---------------------------------------------------------------------------
+template <bool MASK>
+__global__ __launch_bounds__(kBlock) void grad_depth_fused(LaunchArgs la) {
+  constexpr int MODE = PF_IMPLICIT;  // 4-row rounds, runs of 4: five FP64 channels in 46 KB
+  using TL = Tiling<MODE>;
+  const Job& job = la.jobs[0];
+  const int wg = int(blockIdx.x);
+  const int H = job.H, W = job.W, k = job.k, r = job.k / 2;
+  const int64_t plane = int64_t(H) * W;
+  const double* gws = la.gws;
+
+  __shared__ double s_a[TL::rows * kPitch];
+  __shared__ double s_e[TL::rows * kPitch];
+  __shared__ double s_gx[TL::rows * kPitch];
+  __shared__ double s_gy[TL::rows * kPitch];
+  __shared__ double s_ygy[TL::rows * kPitch];
+
+  const int tid = threadIdx.x;
+  const int n_strips = job.n_strips;
+  const int strip = wg % n_strips, band = wg / n_strips;
+  const int ox0 = strip * job.tile_w, ix0 = ox0 - r, x = ix0 + tid;
+  const int yb = band * job.tile_h, ye = min(yb + job.tile_h, H);
+  const int y_ref = yb + job.tile_h / 2;
+  const bool col_used = tid < job.tile_w + k - 1 && x >= 0 && x < W;
+
+  struct C5 {
+    double a, e, gx, gy, ygy;
+  };
+  auto load = [&](int y, C5& c) {
+    c.a = c.e = c.gx = c.gy = c.ygy = 0.0;
+    if (!col_used || y < 0 || y >= H) return;
+    const int64_t p = int64_t(y) * W + x;
+    c.a = gws[p];
+    c.gx = gws[plane + p];
+    c.gy = gws[2 * plane + p];
+    c.e = gws[3 * plane + p];
+    c.ygy = double(y - y_ref) * c.gy;
+  };
+  C5 lead = {0, 0, 0, 0, 0}, lag = {0, 0, 0, 0, 0};
+  auto add = [](C5& s, const C5& c) {
+    s.a += c.a; s.e += c.e; s.gx += c.gx; s.gy += c.gy; s.ygy += c.ygy;
+  };
+  for (int i = 0; i < k - 1; ++i) {
+    C5 c;
+    load(yb - r + i, c);
+    add(lead, c);
+  }
+  const int li = lds_index<MODE>(tid);
+  const int hj = tid / (kBlock / TL::run), run = tid % (kBlock / TL::run);
+  const int o0 = run * TL::run, o1 = min(o0 + TL::run, job.tile_w);
+  for (int yg = yb; yg < ye; yg += TL::rows) {
+    const int nr = min(TL::rows, ye - yg);
+    for (int j = 0; j < TL::rows; ++j) {
+      if (j < nr) {
+        const int y0 = yg + j;
+        C5 c;
+        load(y0 + r, c);
+        add(lead, c);
+        if (y0 > yb) {
+          load(y0 - r - 1, c);
+          add(lag, c);
+        }
+        s_a[j * kPitch + li] = lead.a - lag.a;
+        s_e[j * kPitch + li] = lead.e - lag.e;
+        s_gx[j * kPitch + li] = lead.gx - lag.gx;
+        s_gy[j * kPitch + li] = lead.gy - lag.gy;
+        s_ygy[j * kPitch + li] = lead.ygy - lag.ygy;
+      }
+    }
+    __syncthreads();
+    if (hj < nr && o0 < o1) {
+      const int y0 = yg + hj;
+      const double* ra = s_a + hj * kPitch;
+      const double* re = s_e + hj * kPitch;
+      const double* rgx = s_gx + hj * kPitch;
+      const double* rgy = s_gy + hj * kPitch;
+      const double* rygy = s_ygy + hj * kPitch;
+      const int base = o0 + r;
+      double h[6] = {0, 0, 0, 0, 0, 0}, g[6] = {0, 0, 0, 0, 0, 0};  // a, e, gx, xgx, gy, ygy
+      auto acc = [&](double* s6, int i) {
+        const int l = lds_index<MODE>(i);
+        const double vx = rgx[l];
+        s6[0] += ra[l];
+        s6[1] += re[l];
+        s6[2] += vx;
+        s6[3] += double(i - base) * vx;
+        s6[4] += rgy[l];
+        s6[5] += rygy[l];
+      };
+      for (int i = o0; i < o0 + k - 1; ++i) acc(h, i);
+      for (int q = 0; q < o1 - o0; ++q) {
+        const int o = o0 + q;
+        acc(h, o + k - 1);
+        const double A = h[0] - g[0], E = h[1] - g[1];
+        const double Bx = (h[3] - g[3]) - double(q) * (h[2] - g[2]);
+        const double By = (h[5] - g[5]) - double(y0 - y_ref) * (h[4] - g[4]);
+        acc(g, o);
+        const int xi = ox0 + o;
+        if (xi < W) {
+          float z = job.depth[int64_t(y0) * job.depth_pitch + xi];
+          if (MASK && job.mask && job.mask[int64_t(y0) * job.mask_pitch + xi] == 0) z = 0.0f;
+          double dz = 0.0;
+          if (depth_valid(z)) {
+            const double w = 1.0 / double(z);
+            dz = -(A - Bx - By + 2.0 * w * E) * w * w;
+          }
+          job.normals[int64_t(y0) * W + xi] = float(dz);
+        }
       }
     }
     __syncthreads();
@@ -1076,6 +1369,80 @@ pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_p
   if (!plan) return PF_ERR_NULL;
   const pf_frame_io f = {depth, depth_pitch, mask, mask_pitch, normals, offsets, residuals, status};
   return pf_fit_planes_batch(&plan, &f, 1, stream);
+}
+
+size_t pf_backward_workspace_bytes(const pf_plan* plan) {
+  return plan ? size_t(4) * sizeof(double) * size_t(plan->H) * size_t(plan->W) : 0;
+}
+
+pf_status pf_fit_planes_backward(const pf_plan* plan, const float* depth, int64_t depth_pitch,
+                                 const uint8_t* mask, int64_t mask_pitch,
+                                 const float* grad_normals, const float* grad_offsets,
+                                 const float* grad_residuals, float* grad_depth, void* workspace,
+                                 size_t workspace_bytes, void* stream) {
+  if (!plan || !depth || !grad_depth) return PF_ERR_NULL;
+  if (depth_pitch < plan->W || depth_pitch > INT32_MAX ||
+      (mask && (mask_pitch < plan->W || mask_pitch > INT32_MAX)))
+    return PF_ERR_PITCH;
+  auto misaligned = [](const void* q, uintptr_t m) { return (reinterpret_cast<uintptr_t>(q) & m) != 0; };
+  if (misaligned(depth, 3) || misaligned(grad_depth, 3) || (grad_normals && misaligned(grad_normals, 3)) ||
+      (grad_offsets && misaligned(grad_offsets, 3)) || (grad_residuals && misaligned(grad_residuals, 3)))
+    return PF_ERR_ALIGNMENT;
+  if (!workspace || workspace_bytes < pf_backward_workspace_bytes(plan) || misaligned(workspace, 7))
+    return PF_ERR_WORKSPACE;
+  LaunchArgs la;
+  std::memset(&la, 0, sizeof(la));
+  la.n_jobs = 1;
+  la.kappa_flag = 0.0;
+  la.kappa_fp64 = kDefaultKappaFp64;
+  la.gws = static_cast<double*>(workspace);
+  Job& jb = la.jobs[0];
+  jb.depth = depth;
+  jb.mask = mask;
+  // the backward sweep reads the upstream output gradients through the output slots
+  jb.normals = const_cast<float*>(grad_normals);
+  jb.offsets = const_cast<float*>(grad_offsets);
+  jb.residuals = const_cast<float*>(grad_residuals);
+  jb.status = nullptr;
+  jb.fx = plan->intr.fx;
+  jb.fy = plan->intr.fy;
+  jb.cx = plan->intr.cx;
+  jb.cy = plan->intr.cy;
+  jb.depth_pitch = int32_t(depth_pitch);
+  jb.mask_pitch = mask ? int32_t(mask_pitch) : 0;
+  jb.H = int32_t(plan->H);
+  jb.W = int32_t(plan->W);
+  jb.k = plan->k;
+  jb.tile_w = plan->tile_w;
+  jb.tile_h = plan->tile_h;
+  jb.n_strips = plan->n_strips;
+  jb.wg_begin = 0;
+  jb.vec_store = 0;
+  const int n_wg = plan->n_strips * plan->n_bands;
+  la.n_wg = n_wg;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const dim3 grid(static_cast<unsigned>(n_wg));
+  const dim3 block(kBlock);
+  const bool expl = plan->params.mode == PF_EXPLICIT;
+  if (expl) {
+    if (mask) hipLaunchKernelGGL((fit_planes_fused<double, PF_EXPLICIT, true, true>), grid, block, 0, s, la);
+    else hipLaunchKernelGGL((fit_planes_fused<double, PF_EXPLICIT, false, true>), grid, block, 0, s, la);
+  } else {
+    if (mask) hipLaunchKernelGGL((fit_planes_fused<double, PF_IMPLICIT, true, true>), grid, block, 0, s, la);
+    else hipLaunchKernelGGL((fit_planes_fused<double, PF_IMPLICIT, false, true>), grid, block, 0, s, la);
+  }
+  hipError_t err = hipGetLastError();
+  if (err == hipSuccess) {
+    jb.normals = grad_depth;  // second sweep writes dL/dZ through this slot
+    if (mask) hipLaunchKernelGGL((grad_depth_fused<true>), grid, block, 0, s, la);
+    else hipLaunchKernelGGL((grad_depth_fused<false>), grid, block, 0, s, la);
+    err = hipGetLastError();
+  }
+  if (err != hipSuccess) {
+    g_last_hip_error = int(err);
+    return PF_ERR_HIP;
+  }
+  return PF_OK;
 }
 
 }  // extern "C"

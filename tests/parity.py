@@ -110,3 +110,37 @@ def assert_parity(rep, *, angle_tol=ANGLE_TOL, offset_tol=OFFSET_TOL):
 def oracle_full(frame_depth, intrinsics, k, mode, mask=None, threads=0):
     return oracle.fit_planes(frame_depth.astype(np.float64), intrinsics, k, mode, mask=mask,
                              threads=threads)
+
+
+# --- helpers of the gradient tests ---------------------------------------
+
+def crop(f, x0, y0, w, h):
+    fx, fy, cx, cy = f.intrinsics
+    return f.depth[y0:y0 + h, x0:x0 + w].astype(np.float64), (fx, fy, cx - x0, cy - y0)
+
+
+def upstream(o, seed, mode, kappa_max=1e3, min_offset_frac=0.02, depth=None, intr=None):
+    """Seeded upstream gradients, zero outside well-posed windows (valid,
+    implicit kappa below kappa_max, offset not near the sign flip d = 0)."""
+    H, W = o["offsets"].shape
+    rng = np.random.Generator(np.random.PCG64(seed))
+    keep = o["status"] == 0
+    if mode == "implicit":
+        keep &= o["kappa"] < kappa_max
+    if depth is not None:
+        fx, fy, cx, cy = intr
+        ys, xs = np.mgrid[0:H, 0:W]
+        pc = depth * np.sqrt(((xs - cx) / fx) ** 2 + ((ys - cy) / fy) ** 2 + 1)
+        keep &= np.abs(o["offsets"]) > min_offset_frac * pc
+    gn = rng.standard_normal((3, H, W)) * keep
+    gd = rng.standard_normal((H, W)) * keep
+    gr = rng.standard_normal((H, W)) * keep
+    return gn, gd, gr, keep
+
+
+def loss_oracle(z, intr, k, mode, gn, gd, gr):
+    o = oracle.fit_planes(z, intr, k, mode)
+    m = o["status"] == 0
+    n = np.where(m, o["normals"], 0.0)
+    return float((gn * n).sum() + (gd * np.where(m, o["offsets"], 0)).sum()
+                 + (gr * np.where(m, o["residuals"], 0)).sum())

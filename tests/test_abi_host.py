@@ -142,3 +142,28 @@ def test_batch_argument_checks_return_before_launch():
     assert lib.pf_fit_planes_batch(plans2, io, 2, None) == 1         # NULL output in frame 1
     lib.pf_plan_destroy(p1)
     lib.pf_plan_destroy(p2)
+
+
+def test_backward_argument_checks_return_before_launch():
+    """Only error paths of pf_fit_planes_backward: all rejected on the host."""
+    lib = pf.load_library()
+    code, plan = _create(H=48, W=64, k=5)
+    assert code == 0
+    need = lib.pf_backward_workspace_bytes(plan)
+    assert need == 32 * 48 * 64
+    assert lib.pf_backward_workspace_bytes(None) == 0
+    fake = ctypes.c_void_p(0x10000)
+    odd = ctypes.c_void_p(0x10004)   # 4-byte but not 8-byte aligned
+    odd1 = ctypes.c_void_p(0x10001)
+    call = lambda *a: lib.pf_fit_planes_backward(*a)
+    assert call(None, fake, 64, None, 0, None, None, None, fake, fake, need, None) == 1
+    assert call(plan, None, 64, None, 0, None, None, None, fake, fake, need, None) == 1
+    assert call(plan, fake, 64, None, 0, None, None, None, None, fake, need, None) == 1
+    assert call(plan, fake, 63, None, 0, None, None, None, fake, fake, need, None) == 5
+    assert call(plan, fake, 64, fake, 3, None, None, None, fake, fake, need, None) == 5
+    assert call(plan, odd1, 64, None, 0, None, None, None, fake, fake, need, None) == 6
+    assert call(plan, fake, 64, None, 0, odd1, None, None, fake, fake, need, None) == 6
+    assert call(plan, fake, 64, None, 0, None, None, None, fake, None, need, None) == 7
+    assert call(plan, fake, 64, None, 0, None, None, None, fake, fake, need - 1, None) == 7
+    assert call(plan, fake, 64, None, 0, None, None, None, fake, odd, need, None) == 7
+    lib.pf_plan_destroy(plan)

@@ -280,6 +280,18 @@ __device__ inline void add_sample(float z, int y, T w_ref, int y_ref, Cursor<T>&
   c.n += ok ? 1 : 0;
 }
 
+// The same sample taken out again: recomputed with the same operations, so
+// it is the exact value that was added.
+template <typename T>
+__device__ inline void sub_sample(float z, int y, T w_ref, int y_ref, Cursor<T>& c) {
+  const bool ok = depth_valid(z);
+  const T wh = ok ? recip(z, T(0.0f)) - w_ref : T(0.0f);
+  c.w = c.w - wh;
+  c.yw = c.yw - T(y - y_ref) * wh;
+  c.ww = c.ww - wh * wh;
+  c.n -= ok ? 1 : 0;
+}
+
 // ---------------------------------------------------------------------------
 // Symmetric 3x3 smallest eigenpair of a positive semidefinite matrix.
 //
@@ -695,8 +707,13 @@ __device__ inline MomentGrad implicit_adjoint(const FitArgs& a, const Moments<do
 // yb-r .. y0+r and the lag cursor rows yb-r .. y0-r-1, so lead - lag is the
 // column sum over the window rows y0-r .. y0+r.
 // ---------------------------------------------------------------------------
+// Workgroups per CU the register budget is sized for: the implicit forward
+// sweep (32 KB of LDS) is held to 128 VGPRs so that four waves share a SIMD.
+template <typename T, int MODE, bool BWD>
+constexpr int kMinGroups = (MODE == PF_IMPLICIT && !BWD) ? 4 : 1;
+
 template <typename T, int MODE, bool MASK, bool BWD = false>
-__global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
+__global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD>)) void fit_planes_fused(LaunchArgs la) {
   using TL = Tiling<MODE>;
   // which job and which of its workgroups (the job table is uniform: scalar loop)
   int jb = 0;
@@ -783,11 +800,13 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
   else
     w_ref = wc > 0.0 ? T(ws / wc) : T(0);
 
-  Cursor<T> lead, lag;
-  lead.clear();
-  lag.clear();
+  // column window sums, slid down the band: a row enters at the bottom as the
+  // row r + 1 above leaves (the four-corner difference of the column integral
+  // image, up to rounding order, without carrying its two prefix sums)
+  Cursor<T> col;
+  col.clear();
 
-  // warm-up: the lead cursor takes rows yb-r .. yb+r-1, TL::rows loads at a time
+  // warm-up: the column sums take rows yb-r .. yb+r-1, TL::rows loads at a time
   for (int c = 0; c < a.k - 1; c += TL::rows) {
     float z[TL::rows];
 #pragma unroll
@@ -795,7 +814,7 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
       z[j] = (c + j < a.k - 1 && col_used) ? load_depth<MASK>(a, x, yb - a.r + c + j) : 0.0f;
 #pragma unroll
     for (int j = 0; j < TL::rows; ++j)
-      if (c + j < a.k - 1) add_sample<T>(z[j], yb - a.r + c + j, w_ref, y_ref, lead);
+      if (c + j < a.k - 1) add_sample<T>(z[j], yb - a.r + c + j, w_ref, y_ref, col);
   }
 
   // depth samples of the current round, loaded one round ahead
@@ -821,12 +840,12 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
     for (int j = 0; j < TL::rows; ++j) {
       if (j < nr) {
         const int y0 = yg + j;
-        add_sample<T>(zl[j], y0 + a.r, w_ref, y_ref, lead);
-        if (y0 > yb) add_sample<T>(zg[j], y0 - a.r - 1, w_ref, y_ref, lag);
-        sw[j * kPitch + li] = lead.w - lag.w;
-        syw[j * kPitch + li] = lead.yw - lag.yw;
-        sww[j * kPitch + li] = lead.ww - lag.ww;
-        sn[j * kPitch + li] = lead.n - lag.n;
+        if (y0 > yb) sub_sample<T>(zg[j], y0 - a.r - 1, w_ref, y_ref, col);
+        add_sample<T>(zl[j], y0 + a.r, w_ref, y_ref, col);
+        sw[j * kPitch + li] = col.w;
+        syw[j * kPitch + li] = col.yw;
+        sww[j * kPitch + li] = col.ww;
+        sn[j * kPitch + li] = col.n;
       }
     }
     // issue the next round's loads now; they land while the horizontal phase runs
@@ -848,10 +867,9 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
       const T* rww = sww + hj * kPitch;
       const int* rn = sn + hj * kPitch;
       const int base = o0 + a.r;  // x - x_c = (i - base) - (o - o0)
+      // window sums slid along the run: column o + k - 1 enters as column o leaves
       T hw = T(0), hx = T(0), hy = T(0), hww = T(0);
       int hn = 0;
-      T gw = T(0), gx = T(0), gy = T(0), gww = T(0);
-      int gn = 0;
 #pragma unroll 4
       for (int i = o0; i < o0 + a.k - 1; ++i) {
         const int l = lds_index<MODE>(i);
@@ -862,40 +880,39 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
         hww += rww[l];
         hn += rn[l];
       }
+      auto enter = [&](int i) {
+        const int l = lds_index<MODE>(i);
+        const T v = rw[l];
+        hw += v;
+        hx += T(i - base) * v;
+        hy += ryw[l];
+        hww += rww[l];
+        hn += rn[l];
+      };
+      auto leave = [&](int i) {
+        const int l = lds_index<MODE>(i);
+        const T v = rw[l];
+        hw = hw - v;
+        hx = hx - T(i - base) * v;
+        hy = hy - ryw[l];
+        hww = hww - rww[l];
+        hn -= rn[l];
+      };
       // one output: advance the lead cursor, take the box sums, solve, advance the lag
       auto step = [&](int q) -> PixelOut {
         const int o = o0 + q;
-        {
-          const int i = o + a.k - 1;
-          const int l = lds_index<MODE>(i);
-          const T v = rw[l];
-          hw += v;
-          hx += T(i - base) * v;
-          hy += ryw[l];
-          hww += rww[l];
-          hn += rn[l];
-        }
-        const T B = hw - gw;
-        const T Fx = hx - gx;
-        const T Fy = hy - gy;
-        const T Q = hww - gww;
-        const int cnt = hn - gn;
-        const T Sxw = Fx - T(q) * B;
-        const T Syw = Fy - T(y0 - y_ref) * B;
+        enter(o + a.k - 1);
+        const T B = hw;
+        const T Q = hww;
+        const int cnt = hn;
+        const T Sxw = hx - T(q) * B;
+        const T Syw = hy - T(y0 - y_ref) * B;
         PixelOut po;
         if constexpr (std::is_same<T, df32>::value)
           po = solve_pixel_df<MODE>(a, B, Sxw, Syw, Q, cnt, w_ref, ox0 + o, y0);
         else
           po = solve_pixel<T, MODE>(a, B, Sxw, Syw, Q, cnt, w_ref, ox0 + o, y0);
-        {
-          const int l = lds_index<MODE>(o);
-          const T v = rw[l];
-          gw += v;
-          gx += T(o - base) * v;
-          gy += ryw[l];
-          gww += rww[l];
-          gn += rn[l];
-        }
+        leave(o);
         return po;
       };
       if constexpr (BWD) {
@@ -904,28 +921,11 @@ __global__ __launch_bounds__(kBlock) void fit_planes_fused(LaunchArgs la) {
 #pragma unroll 1
         for (int q = 0; q < o1 - o0; ++q) {
           const int o = o0 + q;
-          {
-            const int i = o + a.k - 1;
-            const int l = lds_index<MODE>(i);
-            const T v = rw[l];
-            hw += v;
-            hx += T(i - base) * v;
-            hy += ryw[l];
-            hww += rww[l];
-            hn += rn[l];
-          }
-          const double B = hw - gw, Q = hww - gww;
-          const double Sxw = (hx - gx) - double(q) * B, Syw = (hy - gy) - double(y0 - y_ref) * B;
-          const int cnt = hn - gn;
-          {
-            const int l = lds_index<MODE>(o);
-            const T v = rw[l];
-            gw += v;
-            gx += T(o - base) * v;
-            gy += ryw[l];
-            gww += rww[l];
-            gn += rn[l];
-          }
+          enter(o + a.k - 1);
+          const double B = hw, Q = hww;
+          const double Sxw = hx - double(q) * B, Syw = hy - double(y0 - y_ref) * B;
+          const int cnt = hn;
+          leave(o);
           const int x0 = ox0 + o;
           if (x0 >= a.W) continue;
           const int64_t pp = prow + o;
@@ -1227,9 +1227,11 @@ pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t widt
   p->tile_w = int(((width + p->n_strips - 1) / p->n_strips + 3) / 4 * 4);
   // bands: enough workgroups to fill the chip (two resident per CU): one full
   // wave of workgroups for the explicit solve, two for the heavier implicit one
+  // (at least 8 rows for the explicit solve, whose per-band warm-up and
+  // prologue would otherwise outweigh its short per-pixel work)
   const int64_t target_groups = params->mode == PF_EXPLICIT ? 512 : 1024;
   int64_t th = (height * p->n_strips + target_groups - 1) / target_groups;
-  th = std::max<int64_t>(th, 4);
+  th = std::max<int64_t>(th, params->mode == PF_EXPLICIT ? 8 : 4);
   // tuning override of the band height (rows of output per workgroup)
   if (const char* env = std::getenv("PF_TILE_H")) {
     const long v = std::strtol(env, nullptr, 10);

@@ -248,6 +248,50 @@ def diff_measure(torch, pf, np, frames_for, diff_loss_inputs):
     return res
 
 
+def xyz_measure(torch, pf, frames_for):
+    """The paper's comparison (Sec. II-E): the same fits in the standard XYZ
+    formulation (nine depth-dependent window sums) against the RGBD one (four),
+    FP64, one frame per launch, each timed over graph replays of 32 launches
+    on rotating buffer sets."""
+    res = {}
+    for name, k in (("vga_640x480", 9), ("hd_1920x1080", 15)):
+        f = frames_for(name)[0]
+        sets = 8 if name.startswith("hd") else 32
+        rig = Rig(torch, f.depth, sets)
+        for mode in ("implicit", "explicit"):
+            row = {}
+            for kind, call in (("rgbd", pf.fit_planes), ("xyz", pf.fit_planes_xyz)):
+                def run(s, call=call):
+                    call(rig.depth[s], f.intrinsics, k, mode=mode, out=rig.outs[s][0])
+                for i in range(5):
+                    run(i % sets)
+                torch.cuda.synchronize()
+                side = torch.cuda.Stream()
+                side.wait_stream(torch.cuda.current_stream())
+                with torch.cuda.stream(side):
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g, stream=side):
+                        for j in range(32):
+                            run(j % sets)
+                torch.cuda.current_stream().wait_stream(side)
+                g.replay()
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(5):
+                    g.replay()
+                b.record()
+                torch.cuda.synchronize()
+                ms = a.elapsed_time(b) / (5 * 32)
+                row[f"{kind}_ms"] = round(ms, 5)
+                row[f"{kind}_Mpx_s"] = round(f.depth.size / (ms * 1e-3) / 1e6, 1)
+            row["xyz_over_rgbd_time"] = round(row["xyz_ms"] / row["rgbd_ms"], 3)
+            res[f"{name}_k{k}_{mode}"] = row
+        del rig
+        torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(frame, ks, mode, budget_s):
     """The FP64 oracle on the host: random sample of window centres, growing until
     about budget_s seconds of work; returns Mpixel/s and what was sampled."""
@@ -346,6 +390,7 @@ def main():
         torch.cuda.empty_cache()
         extras["batch_mixed_64"] = batch_measure(torch, pf, np, frames_for)
         extras["diff_8x640x480"] = diff_measure(torch, pf, np, frames_for, diff_loss_inputs)
+        extras["xyz_vs_rgbd"] = xyz_measure(torch, pf, frames_for)
         out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(f, ks, "implicit", args.cpu_seconds)

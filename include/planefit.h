@@ -186,6 +186,23 @@ pf_status pf_fit_planes_backward(const pf_plan* plan, const float* depth, int64_
                                  const float* grad_residuals, float* grad_depth, void* workspace,
                                  size_t workspace_bytes, void* stream);
 
+/* The standard formulation, for comparison with the RGBD one (Sec. II, Eq. 3-9):
+ * the same per-pixel k x k window fits computed from window sums of the
+ * back-projected points P = Z (u, v, 1) and their products (nine
+ * depth-dependent channels instead of four).
+ *   PF_IMPLICIT: unit normal of the smallest eigenvalue of the window's point
+ *                covariance (Eq. 3-6, |n| = 1), d = -n . centroid;
+ *   PF_EXPLICIT: Z = a X + b Y + c by least squares (Eq. 7-9); the plane
+ *                (a, b, -1) . P + c = 0 normalised.
+ * Orientation d >= 0.  residuals = RMS point-to-plane distance over the window
+ * (in the depth unit, not divided by Z as in pf_fit_planes).  Validity, NaN
+ * outputs, status bits 0 and 1 (kappa of the covariance) and the buffer
+ * contract are those of pf_fit_planes.  The plan must use PF_PREC_FP64 (else
+ * PF_ERR_UNSUPPORTED); its camera, k and mode are used.  No workspace. */
+pf_status pf_fit_planes_xyz(const pf_plan* plan, const float* depth, int64_t depth_pitch,
+                            const uint8_t* mask, int64_t mask_pitch, float* normals,
+                            float* offsets, float* residuals, uint8_t* status, void* stream);
+
 /* Static description of a status code. */
 const char* pf_status_string(pf_status s);
 

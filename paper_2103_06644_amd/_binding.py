@@ -63,7 +63,7 @@ _lib_lock = threading.Lock()
 
 EXPORTS = ("pf_plan_create", "pf_plan_destroy", "pf_plan_workspace_bytes",
            "pf_plan_camera_moments", "pf_fit_planes", "pf_fit_planes_batch",
-           "pf_backward_workspace_bytes", "pf_fit_planes_backward",
+           "pf_backward_workspace_bytes", "pf_fit_planes_backward", "pf_fit_planes_xyz",
            "pf_status_string", "pf_last_hip_error")
 
 
@@ -98,6 +98,8 @@ def load_library(path: str | None = None):
         lib.pf_fit_planes_backward.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp,
                                                ctypes.c_size_t, vp]
         lib.pf_fit_planes_backward.restype = i32
+        lib.pf_fit_planes_xyz.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp]
+        lib.pf_fit_planes_xyz.restype = i32
         lib.pf_status_string.argtypes = [i32]
         lib.pf_status_string.restype = ctypes.c_char_p
         lib.pf_last_hip_error.argtypes = []
@@ -264,6 +266,35 @@ def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "
             ctypes.c_void_p(normals.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
             ctypes.c_void_p(residuals.data_ptr()), ctypes.c_void_p(status.data_ptr()),
             ctypes.c_void_p(work.data_ptr()) if work is not None else None, ws,
+            _stream_handle(torch, dev, stream))
+    _check(code)
+    return normals, offsets, residuals, status
+
+
+def fit_planes_xyz(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "implicit",
+                   kappa_flag: float = 0.0, out=None, stream=None):
+    """The standard XYZ formulation of the same per-pixel fits (nine
+    depth-dependent window sums instead of four), for comparison; FP64.
+    Same arguments and outputs as fit_planes, except that residuals are RMS
+    point-to-plane distances in the depth unit."""
+    import torch
+    _check_depth(torch, depth)
+    H, W = depth.shape
+    dev = depth.device
+    plan = get_plan(intrinsics, H, W, window, mode, "fp64", kappa_flag)
+    mptr, mpitch = _mask_arg(torch, valid_mask, depth)
+    if out is None:
+        out = (torch.empty((3, H, W), dtype=torch.float32, device=dev),
+               torch.empty((H, W), dtype=torch.float32, device=dev),
+               torch.empty((H, W), dtype=torch.float32, device=dev),
+               torch.empty((H, W), dtype=torch.uint8, device=dev))
+    normals, offsets, residuals, status = out
+    with _on_device(torch, dev):
+        code = plan._lib.pf_fit_planes_xyz(
+            plan.handle, ctypes.c_void_p(depth.data_ptr()), depth.stride(0),
+            ctypes.c_void_p(mptr) if mptr else None, mpitch,
+            ctypes.c_void_p(normals.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+            ctypes.c_void_p(residuals.data_ptr()), ctypes.c_void_p(status.data_ptr()),
             _stream_handle(torch, dev, stream))
     _check(code)
     return normals, offsets, residuals, status

@@ -1155,6 +1155,180 @@ __global__ __launch_bounds__(kBlock) void grad_depth_fused(LaunchArgs la) {
 }
 
 // ---------------------------------------------------------------------------
+// The standard formulation, for comparison (Sec. II, Eq. 3-9): the same
+// sliding-window sweep over the back-projected points P = Z (u, v, 1) instead
+// of the disparity integrands.  Every entry of the scatter matrix of Eq. 5
+// depends on the depth, so nine channels (sums of X, Y, Z and of their six
+// products) plus the count are carried instead of four: the cost the RGBD
+// formulation removes.  FP64 throughout; points are taken relative to a
+// per-band reference point so that the covariance differences stay small.
+//   implicit (Eq. 3-6): n = eigenvector of the smallest eigenvalue of the
+//                       window covariance, d = -n . centroid (|n| = 1);
+//   explicit (Eq. 7-9): Z = a X + b Y + c by centred least squares, i.e. the
+//                       plane (a, b, -1) . P + c = 0, normalised.
+// Orientation d >= 0; residual = RMS point-to-plane distance (depth unit);
+// status bit 1 (implicit) as in the RGBD fit.  Rounds of 2 rows, runs of 2
+// outputs: 10 channels of column sums fit in 44 KB of LDS.
+// ---------------------------------------------------------------------------
+constexpr int kXyzRows = 2, kXyzRun = 2, kXyzSub = kPitch / kXyzRun;
+__device__ inline int xyz_lds_index(int i) { return (i % kXyzRun) * kXyzSub + i / kXyzRun; }
+
+template <int MODE, bool MASK>
+__global__ __launch_bounds__(kBlock) void fit_planes_xyz(LaunchArgs la) {
+  const Job& job = la.jobs[0];
+  const int wg = int(blockIdx.x);
+  const int H = job.H, W = job.W, k = job.k, r = job.k / 2;
+  const int64_t plane = int64_t(H) * W;
+  const int tid = threadIdx.x;
+  const int strip = wg % job.n_strips, band = wg / job.n_strips;
+  const int ox0 = strip * job.tile_w, ix0 = ox0 - r, x = ix0 + tid;
+  const int yb = band * job.tile_h, ye = min(yb + job.tile_h, H);
+  const int y_ref = min(yb + job.tile_h / 2, H - 1);
+  const bool col_used = tid < job.tile_w + k - 1 && x >= 0 && x < W;
+  const double ifx = 1.0 / job.fx, ify = 1.0 / job.fy;
+  const double ux = (double(x) - job.cx) * ifx;
+
+  __shared__ double s_c[9][kXyzRows * kPitch];
+  __shared__ int s_n[kXyzRows * kPitch];
+  __shared__ double red[2 * (kBlock / 64)];
+
+  auto load = [&](int y) -> float {
+    if (!col_used || y < 0 || y >= H) return 0.0f;
+    float z = job.depth[int64_t(y) * job.depth_pitch + x];
+    if (MASK && job.mask && job.mask[int64_t(y) * job.mask_pitch + x] == 0) z = 0.0f;
+    return z;
+  };
+
+  // reference point: mean depth of the band's middle row on the ray of the strip centre
+  double zs = 0.0, zc = 0.0;
+  {
+    const float z = load(y_ref);
+    if (depth_valid(z)) {
+      zs = double(z);
+      zc = 1.0;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      zs += __shfl_down(zs, off, 64);
+      zc += __shfl_down(zc, off, 64);
+    }
+    if ((tid & 63) == 0) {
+      red[2 * (tid >> 6)] = zs;
+      red[2 * (tid >> 6) + 1] = zc;
+    }
+    __syncthreads();
+    zs = 0.0;
+    zc = 0.0;
+    for (int i = 0; i < kBlock / 64; ++i) {
+      zs += red[2 * i];
+      zc += red[2 * i + 1];
+    }
+  }
+  const double Zr = zc > 0.0 ? zs / zc : 1.0;
+  const double Xr = Zr * (double(ox0 + job.tile_w / 2) - job.cx) * ifx;
+  const double Yr = Zr * (double(y_ref) - job.cy) * ify;
+
+  double c[9];
+  int cn = 0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) c[i] = 0.0;
+  // one sample into (sign +1) or out of (sign -1) the column sums
+  auto sample = [&](float z, int y, double sign) {
+    const bool ok = depth_valid(z);
+    const double zd = ok ? double(z) : 0.0;
+    const double px = ok ? zd * ux - Xr : 0.0;
+    const double py = ok ? zd * ((double(y) - job.cy) * ify) - Yr : 0.0;
+    const double pz = ok ? zd - Zr : 0.0;
+    const double sx = sign * px, sy = sign * py, sz = sign * pz;
+    c[0] += sx; c[1] += sy; c[2] += sz;
+    c[3] += sx * px; c[4] += sx * py; c[5] += sx * pz;
+    c[6] += sy * py; c[7] += sy * pz; c[8] += sz * pz;
+    cn += ok ? (sign > 0.0 ? 1 : -1) : 0;
+  };
+  for (int i = 0; i < k - 1; ++i) sample(load(yb - r + i), yb - r + i, 1.0);
+
+  const int li = xyz_lds_index(tid);
+  const int hj = tid / (kBlock / kXyzRun), run = tid % (kBlock / kXyzRun);
+  const int o0 = run * kXyzRun, o1 = min(o0 + kXyzRun, job.tile_w);
+  for (int yg = yb; yg < ye; yg += kXyzRows) {
+    const int nr = min(kXyzRows, ye - yg);
+    for (int j = 0; j < kXyzRows; ++j) {
+      if (j < nr) {
+        const int y0 = yg + j;
+        if (y0 > yb) sample(load(y0 - r - 1), y0 - r - 1, -1.0);
+        sample(load(y0 + r), y0 + r, 1.0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) s_c[i][j * kPitch + li] = c[i];
+        s_n[j * kPitch + li] = cn;
+      }
+    }
+    __syncthreads();
+    if (hj < nr && o0 < o1) {
+      const int y0 = yg + hj;
+      double h[9];
+      int hn = 0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) h[i] = 0.0;
+      auto move = [&](int i, double sign) {
+        const int l = xyz_lds_index(i);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) h[t] += sign * s_c[t][hj * kPitch + l];
+        hn += sign > 0.0 ? s_n[hj * kPitch + l] : -s_n[hj * kPitch + l];
+      };
+      for (int i = o0; i < o0 + k - 1; ++i) move(i, 1.0);
+      for (int q = 0; q < o1 - o0; ++q) {
+        const int o = o0 + q;
+        move(o + k - 1, 1.0);
+        const int xo = ox0 + o;
+        float on0 = __builtin_nanf(""), on1 = on0, on2 = on0, od = on0, ores = on0;
+        uint8_t st = 1;
+        if (hn == k * k && xo < W) {
+          const double iN = 1.0 / double(k * k);
+          const double mx = h[0] * iN, my = h[1] * iN, mz = h[2] * iN;
+          const double cxx = h[3] - h[0] * mx, cxy = h[4] - h[0] * my, cxz = h[5] - h[0] * mz;
+          const double cyy = h[6] - h[1] * my, cyz = h[7] - h[1] * mz, czz = h[8] - h[2] * mz;
+          const double Mx = mx + Xr, My = my + Yr, Mz = mz + Zr;
+          double n0, n1, n2, d, res;
+          st = 0;
+          if (MODE == PF_IMPLICIT) {
+            const Eig3<double> e = smallest_eig<double>(cxx, cxy, cxz, cyy, cyz, czz);
+            n0 = e.n[0]; n1 = e.n[1]; n2 = e.n[2];
+            d = -(n0 * Mx + n1 * My + n2 * Mz);
+            res = sqrt(fmax(e.l1, 0.0) * iN);
+            const double gap = e.l2 - e.l1;
+            const double kap = (e.degenerate || !(gap > 0.0)) ? __builtin_inf() : e.l3 / gap;
+            if (la.kappa_flag > 0.0 && !(kap <= la.kappa_flag)) st = 2;
+          } else {
+            const double det = cxx * cyy - cxy * cxy;
+            const double idet = 1.0 / det;
+            const double aa = (cxz * cyy - cyz * cxy) * idet, bb = (cyz * cxx - cxz * cxy) * idet;
+            const double cc = Mz - aa * Mx - bb * My;
+            const double is = 1.0 / sqrt(aa * aa + bb * bb + 1.0);
+            n0 = aa * is; n1 = bb * is; n2 = -is;
+            d = cc * is;
+            res = sqrt(fmax(czz - aa * cxz - bb * cyz, 0.0) * iN) * is;
+          }
+          if (d < 0.0) {
+            d = -d; n0 = -n0; n1 = -n1; n2 = -n2;
+          }
+          on0 = float(n0); on1 = float(n1); on2 = float(n2); od = float(d); ores = float(res);
+        }
+        if (xo < W) {
+          const int64_t pp = int64_t(y0) * W + xo;
+          job.normals[pp] = on0;
+          job.normals[plane + pp] = on1;
+          job.normals[2 * plane + pp] = on2;
+          job.offsets[pp] = od;
+          job.residuals[pp] = ores;
+          if (job.status) job.status[pp] = st;
+        }
+        move(o, -1.0);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
 thread_local int g_last_hip_error = 0;
@@ -1440,6 +1614,60 @@ pf_status pf_fit_planes_backward(const pf_plan* plan, const float* depth, int64_
     else hipLaunchKernelGGL((grad_depth_fused<false>), grid, block, 0, s, la);
     err = hipGetLastError();
   }
+  if (err != hipSuccess) {
+    g_last_hip_error = int(err);
+    return PF_ERR_HIP;
+  }
+  return PF_OK;
+}
+
+pf_status pf_fit_planes_xyz(const pf_plan* plan, const float* depth, int64_t depth_pitch,
+                            const uint8_t* mask, int64_t mask_pitch, float* normals,
+                            float* offsets, float* residuals, uint8_t* status, void* stream) {
+  if (!plan || !depth || !normals || !offsets || !residuals) return PF_ERR_NULL;
+  if (plan->params.precision != PF_PREC_FP64) return PF_ERR_UNSUPPORTED;
+  if (depth_pitch < plan->W || depth_pitch > INT32_MAX ||
+      (mask && (mask_pitch < plan->W || mask_pitch > INT32_MAX)))
+    return PF_ERR_PITCH;
+  auto misaligned = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 3) != 0; };
+  if (misaligned(depth) || misaligned(normals) || misaligned(offsets) || misaligned(residuals))
+    return PF_ERR_ALIGNMENT;
+  LaunchArgs la;
+  std::memset(&la, 0, sizeof(la));
+  la.n_jobs = 1;
+  la.kappa_flag = plan->params.kappa_flag;
+  Job& jb = la.jobs[0];
+  jb.depth = depth;
+  jb.mask = mask;
+  jb.normals = normals;
+  jb.offsets = offsets;
+  jb.residuals = residuals;
+  jb.status = status;
+  jb.fx = plan->intr.fx;
+  jb.fy = plan->intr.fy;
+  jb.cx = plan->intr.cx;
+  jb.cy = plan->intr.cy;
+  jb.depth_pitch = int32_t(depth_pitch);
+  jb.mask_pitch = mask ? int32_t(mask_pitch) : 0;
+  jb.H = int32_t(plan->H);
+  jb.W = int32_t(plan->W);
+  jb.k = plan->k;
+  jb.tile_w = plan->tile_w;
+  jb.tile_h = plan->tile_h;
+  jb.n_strips = plan->n_strips;
+  const int n_wg = plan->n_strips * plan->n_bands;
+  la.n_wg = n_wg;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const dim3 grid(static_cast<unsigned>(n_wg));
+  const dim3 block(kBlock);
+  if (plan->params.mode == PF_EXPLICIT) {
+    if (mask) hipLaunchKernelGGL((fit_planes_xyz<PF_EXPLICIT, true>), grid, block, 0, s, la);
+    else hipLaunchKernelGGL((fit_planes_xyz<PF_EXPLICIT, false>), grid, block, 0, s, la);
+  } else {
+    if (mask) hipLaunchKernelGGL((fit_planes_xyz<PF_IMPLICIT, true>), grid, block, 0, s, la);
+    else hipLaunchKernelGGL((fit_planes_xyz<PF_IMPLICIT, false>), grid, block, 0, s, la);
+  }
+  const hipError_t err = hipGetLastError();
   if (err != hipSuccess) {
     g_last_hip_error = int(err);
     return PF_ERR_HIP;

@@ -167,3 +167,20 @@ def test_backward_argument_checks_return_before_launch():
     assert call(plan, fake, 64, None, 0, None, None, None, fake, fake, need - 1, None) == 7
     assert call(plan, fake, 64, None, 0, None, None, None, fake, odd, need, None) == 7
     lib.pf_plan_destroy(plan)
+
+
+def test_xyz_argument_checks_return_before_launch():
+    lib = pf.load_library()
+    code, plan = _create(H=48, W=64, k=5)
+    code32, plan32 = _create(H=48, W=64, k=5, prec=1)
+    assert code == 0 and code32 == 0
+    fake = ctypes.c_void_p(0x10000)
+    odd = ctypes.c_void_p(0x10001)
+    call = lambda *a: lib.pf_fit_planes_xyz(*a)
+    assert call(None, fake, 64, None, 0, fake, fake, fake, None, None) == 1
+    assert call(plan, fake, 64, None, 0, None, fake, fake, None, None) == 1
+    assert call(plan32, fake, 64, None, 0, fake, fake, fake, None, None) == 8
+    assert call(plan, fake, 60, None, 0, fake, fake, fake, None, None) == 5
+    assert call(plan, odd, 64, None, 0, fake, fake, fake, None, None) == 6
+    lib.pf_plan_destroy(plan)
+    lib.pf_plan_destroy(plan32)

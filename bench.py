@@ -188,8 +188,8 @@ def batch_measure(torch, pf, np, frames_for):
 def diff_measure(torch, pf, np, frames_for, diff_loss_inputs):
     """The differentiation workload: 8 frames of 640x480, k = 9, implicit FP64.
     One step = the forward fits of the 8 frames (one batched launch) and the
-    backward pass of each frame for L = sum W (1 - n . t) + 0.1 r (two launches
-    per frame), replayed from a captured HIP graph; the backward alone is timed
+    batched backward pass of the 8 frames for L = sum W (1 - n . t) + 0.1 r (two
+    launches), replayed from a captured HIP graph; the backward alone is timed
     the same way."""
     frames = frames_for("diff_8x640x480")
     k = frames[0].window
@@ -212,8 +212,8 @@ def diff_measure(torch, pf, np, frames_for, diff_loss_inputs):
         pf.fit_planes_batch(depth, intr, k, mode="implicit", outs=outs)
 
     def bwd():
-        for i in range(len(frames)):
-            pf.fit_planes_backward(depth[i], intr, k, ups[i][0], None, ups[i][1], out=grads[i])
+        pf.fit_planes_backward_batch(depth, intr, k, [u[0] for u in ups], None,
+                                     [u[1] for u in ups], outs=grads)
 
     def both():
         fwd()

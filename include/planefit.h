@@ -186,6 +186,31 @@ pf_status pf_fit_planes_backward(const pf_plan* plan, const float* depth, int64_
                                  const float* grad_residuals, float* grad_depth, void* workspace,
                                  size_t workspace_bytes, void* stream);
 
+/* Buffers of one frame for pf_fit_planes_backward_batch (same meaning, layout
+ * and ownership as the arguments of pf_fit_planes_backward). */
+typedef struct {
+  const float* depth;
+  int64_t depth_pitch;
+  const uint8_t* mask;            /* or NULL */
+  int64_t mask_pitch;
+  const float* grad_normals;      /* [3][H][W] or NULL */
+  const float* grad_offsets;      /* [H][W] or NULL */
+  const float* grad_residuals;    /* [H][W] or NULL */
+  float* grad_depth;              /* [H][W], written */
+} pf_backward_io;
+
+/* The backward pass of n frames in as few launches as possible (two launches
+ * per group of up to 32 frames of any sizes and window sizes; Sec. II-C: many
+ * fits from one pass over each frame).  All plans must share the mode (else
+ * PF_ERR_UNSUPPORTED).  The workspace must hold the sum over the frames of
+ * pf_backward_workspace_bytes (8-byte aligned); frame i uses its own region,
+ * in order.  Each frame is checked on the host as in pf_fit_planes_backward
+ * before anything is enqueued; n = 0 is a no-op.  Results are bit-identical to
+ * one pf_fit_planes_backward call per frame. */
+pf_status pf_fit_planes_backward_batch(const pf_plan* const* plans, const pf_backward_io* io,
+                                       int32_t n, void* workspace, size_t workspace_bytes,
+                                       void* stream);
+
 /* The standard formulation, for comparison with the RGBD one (Sec. II, Eq. 3-9):
  * the same per-pixel k x k window fits computed from window sums of the
  * back-projected points P = Z (u, v, 1) and their products (nine

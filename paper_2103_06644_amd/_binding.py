@@ -52,6 +52,13 @@ class _FrameIO(ctypes.Structure):
                 ("residuals", ctypes.c_void_p), ("status", ctypes.c_void_p)]
 
 
+class _BackwardIO(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_void_p), ("depth_pitch", ctypes.c_int64),
+                ("mask", ctypes.c_void_p), ("mask_pitch", ctypes.c_int64),
+                ("grad_normals", ctypes.c_void_p), ("grad_offsets", ctypes.c_void_p),
+                ("grad_residuals", ctypes.c_void_p), ("grad_depth", ctypes.c_void_p)]
+
+
 class _Params(ctypes.Structure):
     _fields_ = [("window", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
@@ -63,7 +70,8 @@ _lib_lock = threading.Lock()
 
 EXPORTS = ("pf_plan_create", "pf_plan_destroy", "pf_plan_workspace_bytes",
            "pf_plan_camera_moments", "pf_fit_planes", "pf_fit_planes_batch",
-           "pf_backward_workspace_bytes", "pf_fit_planes_backward", "pf_fit_planes_xyz",
+           "pf_backward_workspace_bytes", "pf_fit_planes_backward",
+           "pf_fit_planes_backward_batch", "pf_fit_planes_xyz",
            "pf_status_string", "pf_last_hip_error")
 
 
@@ -98,6 +106,10 @@ def load_library(path: str | None = None):
         lib.pf_fit_planes_backward.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp,
                                                ctypes.c_size_t, vp]
         lib.pf_fit_planes_backward.restype = i32
+        lib.pf_fit_planes_backward_batch.argtypes = [ctypes.POINTER(vp),
+                                                     ctypes.POINTER(_BackwardIO), i32, vp,
+                                                     ctypes.c_size_t, vp]
+        lib.pf_fit_planes_backward_batch.restype = i32
         lib.pf_fit_planes_xyz.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp]
         lib.pf_fit_planes_xyz.restype = i32
         lib.pf_status_string.argtypes = [i32]
@@ -405,6 +417,62 @@ def fit_planes_backward(depth, intrinsics, window: int, grad_normals=None, grad_
             _stream_handle(torch, dev, stream))
     _check(code)
     return out
+
+
+def _grad_arg(torch, g, shp, dev):
+    if g is None:
+        return None
+    if (tuple(g.shape) != shp or g.dtype != torch.float32 or not g.is_contiguous()
+            or g.device != dev):
+        raise ValueError(f"output gradients must be contiguous float32 {shp} on depth's device")
+    return g.data_ptr()
+
+
+def fit_planes_backward_batch(depths, intrinsics, windows, grad_normals=None, grad_offsets=None,
+                              grad_residuals=None, valid_masks=None, *, mode="implicit",
+                              outs=None, stream=None):
+    """The backward pass of several frames (any sizes, per-frame k) in two
+    launches per 32 frames.  Per-frame lists of output gradients (entries or
+    whole lists may be None); returns the list of dL/dZ tensors."""
+    import torch
+    n = len(depths)
+    if n == 0:
+        return []
+    intr = list(intrinsics) if isinstance(intrinsics[0], (tuple, list)) else [intrinsics] * n
+    ks = list(windows) if isinstance(windows, (tuple, list)) else [windows] * n
+    lists = [list(x) if x is not None else [None] * n
+             for x in (grad_normals, grad_offsets, grad_residuals, valid_masks)]
+    if not all(len(x) == n for x in [intr, ks] + lists):
+        raise ValueError("per-frame argument lists must have one entry per frame")
+    dev = depths[0].device
+    plans, ios, results = [], (_BackwardIO * n)(), []
+    ws = 0
+    for i, d in enumerate(depths):
+        _check_depth(torch, d)
+        if d.device != dev:
+            raise ValueError("all frames must be on one device")
+        H, W = d.shape
+        p = get_plan(intr[i], H, W, ks[i], mode, "fp64", 0.0)
+        plans.append(p)
+        ws += p.backward_workspace_bytes
+        mptr, mpitch = _mask_arg(torch, lists[3][i], d)
+        out = torch.empty((H, W), dtype=torch.float32, device=dev) if outs is None else outs[i]
+        if (tuple(out.shape) != (H, W) or out.dtype != torch.float32 or not out.is_contiguous()
+                or out.device != dev):
+            raise ValueError("outs must be contiguous float32 [H, W] tensors on depth's device")
+        results.append(out)
+        ios[i] = _BackwardIO(d.data_ptr(), d.stride(0), mptr, mpitch,
+                             _grad_arg(torch, lists[0][i], (3, H, W), dev),
+                             _grad_arg(torch, lists[1][i], (H, W), dev),
+                             _grad_arg(torch, lists[2][i], (H, W), dev), out.data_ptr())
+    work = torch.empty(ws, dtype=torch.uint8, device=dev)
+    handles = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    lib = load_library()
+    with _on_device(torch, dev):
+        code = lib.pf_fit_planes_backward_batch(handles, ios, n, ctypes.c_void_p(work.data_ptr()),
+                                                ws, _stream_handle(torch, dev, stream))
+    _check(code)
+    return results
 
 
 def _autograd_function():

@@ -707,6 +707,14 @@ __device__ inline MomentGrad implicit_adjoint(const FitArgs& a, const Moments<do
 // yb-r .. y0+r and the lag cursor rows yb-r .. y0-r-1, so lead - lag is the
 // column sum over the window rows y0-r .. y0+r.
 // ---------------------------------------------------------------------------
+// Backward launches give every job a region of 4 H W doubles of the workspace,
+// in job order (a uniform scan of the job table).
+__device__ inline int64_t bwd_ws_offset(const LaunchArgs& la, int jb) {
+  int64_t off = 0;
+  for (int i = 0; i < jb; ++i) off += 4 * int64_t(la.jobs[i].H) * la.jobs[i].W;
+  return off;
+}
+
 // Workgroups per CU the register budget is sized for: the implicit forward
 // sweep (32 KB of LDS) is held to 128 VGPRs so that four waves share a SIMD.
 template <typename T, int MODE, bool BWD>
@@ -751,7 +759,8 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD>)) void fit_planes
   a.kappa_flag = la.kappa_flag;
   a.kappa_fp64 = la.kappa_fp64;
   a.vec_store = job.vec_store;
-  a.gws = la.gws;
+  a.gws = nullptr;
+  if constexpr (BWD) a.gws = la.gws + bwd_ws_offset(la, jb);
 
   __shared__ T sw[TL::rows * kPitch];
   __shared__ T syw[TL::rows * kPitch];
@@ -1045,11 +1054,13 @@ template <bool MASK>
 __global__ __launch_bounds__(kBlock) void grad_depth_fused(LaunchArgs la) {
   constexpr int MODE = PF_IMPLICIT;  // 4-row rounds, runs of 4: five FP64 channels in 46 KB
   using TL = Tiling<MODE>;
-  const Job& job = la.jobs[0];
-  const int wg = int(blockIdx.x);
+  int jb = 0;
+  while (jb + 1 < la.n_jobs && int(blockIdx.x) >= la.jobs[jb + 1].wg_begin) ++jb;
+  const Job& job = la.jobs[jb];
+  const int wg = int(blockIdx.x) - job.wg_begin;
   const int H = job.H, W = job.W, k = job.k, r = job.k / 2;
   const int64_t plane = int64_t(H) * W;
-  const double* gws = la.gws;
+  const double* gws = la.gws + bwd_ws_offset(la, jb);
 
   __shared__ double s_a[TL::rows * kPitch];
   __shared__ double s_e[TL::rows * kPitch];
@@ -1551,74 +1562,109 @@ size_t pf_backward_workspace_bytes(const pf_plan* plan) {
   return plan ? size_t(4) * sizeof(double) * size_t(plan->H) * size_t(plan->W) : 0;
 }
 
+pf_status pf_fit_planes_backward_batch(const pf_plan* const* plans, const pf_backward_io* io,
+                                       int32_t n, void* workspace, size_t workspace_bytes,
+                                       void* stream) {
+  if (n < 0) return PF_ERR_SHAPE;
+  if (n == 0) return PF_OK;
+  if (!plans || !io) return PF_ERR_NULL;
+  auto misaligned = [](const void* q, uintptr_t m) {
+    return (reinterpret_cast<uintptr_t>(q) & m) != 0;
+  };
+  size_t need = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const pf_plan* p = plans[i];
+    const pf_backward_io& f = io[i];
+    if (!p || !f.depth || !f.grad_depth) return PF_ERR_NULL;
+    if (f.depth_pitch < p->W || f.depth_pitch > INT32_MAX ||
+        (f.mask && (f.mask_pitch < p->W || f.mask_pitch > INT32_MAX)))
+      return PF_ERR_PITCH;
+    if (misaligned(f.depth, 3) || misaligned(f.grad_depth, 3) ||
+        (f.grad_normals && misaligned(f.grad_normals, 3)) ||
+        (f.grad_offsets && misaligned(f.grad_offsets, 3)) ||
+        (f.grad_residuals && misaligned(f.grad_residuals, 3)))
+      return PF_ERR_ALIGNMENT;
+    if (p->params.mode != plans[0]->params.mode) return PF_ERR_UNSUPPORTED;
+    need += pf_backward_workspace_bytes(p);
+  }
+  if (!workspace || workspace_bytes < need || misaligned(workspace, 7)) return PF_ERR_WORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool expl = plans[0]->params.mode == PF_EXPLICIT;
+  double* ws = static_cast<double*>(workspace);
+  for (int32_t first = 0; first < n; first += kMaxJobs) {
+    const int32_t cnt = std::min<int32_t>(kMaxJobs, n - first);
+    LaunchArgs la;
+    std::memset(&la, 0, sizeof(la));
+    la.n_jobs = cnt;
+    la.kappa_flag = 0.0;
+    la.kappa_fp64 = kDefaultKappaFp64;
+    la.gws = ws;
+    bool has_mask = false;
+    int32_t wg = 0;
+    for (int32_t j = 0; j < cnt; ++j) {
+      const pf_plan* p = plans[first + j];
+      const pf_backward_io& f = io[first + j];
+      Job& jb = la.jobs[j];
+      jb.depth = f.depth;
+      jb.mask = f.mask;
+      // the first sweep reads the upstream output gradients through the output slots
+      jb.normals = const_cast<float*>(f.grad_normals);
+      jb.offsets = const_cast<float*>(f.grad_offsets);
+      jb.residuals = const_cast<float*>(f.grad_residuals);
+      jb.status = nullptr;
+      jb.fx = p->intr.fx;
+      jb.fy = p->intr.fy;
+      jb.cx = p->intr.cx;
+      jb.cy = p->intr.cy;
+      jb.depth_pitch = int32_t(f.depth_pitch);
+      jb.mask_pitch = f.mask ? int32_t(f.mask_pitch) : 0;
+      jb.H = int32_t(p->H);
+      jb.W = int32_t(p->W);
+      jb.k = p->k;
+      jb.tile_w = p->tile_w;
+      jb.tile_h = p->tile_h;
+      jb.n_strips = p->n_strips;
+      jb.wg_begin = wg;
+      jb.vec_store = 0;
+      has_mask = has_mask || f.mask != nullptr;
+      wg += p->n_strips * p->n_bands;
+      ws += 4 * int64_t(p->H) * p->W;
+    }
+    la.n_wg = wg;
+    const dim3 grid(static_cast<unsigned>(wg));
+    const dim3 block(kBlock);
+    if (expl) {
+      if (has_mask) hipLaunchKernelGGL((fit_planes_fused<double, PF_EXPLICIT, true, true>), grid, block, 0, s, la);
+      else hipLaunchKernelGGL((fit_planes_fused<double, PF_EXPLICIT, false, true>), grid, block, 0, s, la);
+    } else {
+      if (has_mask) hipLaunchKernelGGL((fit_planes_fused<double, PF_IMPLICIT, true, true>), grid, block, 0, s, la);
+      else hipLaunchKernelGGL((fit_planes_fused<double, PF_IMPLICIT, false, true>), grid, block, 0, s, la);
+    }
+    hipError_t err = hipGetLastError();
+    if (err == hipSuccess) {
+      // the second sweep writes dL/dZ through the normals slot
+      for (int32_t j = 0; j < cnt; ++j) la.jobs[j].normals = io[first + j].grad_depth;
+      if (has_mask) hipLaunchKernelGGL((grad_depth_fused<true>), grid, block, 0, s, la);
+      else hipLaunchKernelGGL((grad_depth_fused<false>), grid, block, 0, s, la);
+      err = hipGetLastError();
+    }
+    if (err != hipSuccess) {
+      g_last_hip_error = int(err);
+      return PF_ERR_HIP;
+    }
+  }
+  return PF_OK;
+}
+
 pf_status pf_fit_planes_backward(const pf_plan* plan, const float* depth, int64_t depth_pitch,
                                  const uint8_t* mask, int64_t mask_pitch,
                                  const float* grad_normals, const float* grad_offsets,
                                  const float* grad_residuals, float* grad_depth, void* workspace,
                                  size_t workspace_bytes, void* stream) {
-  if (!plan || !depth || !grad_depth) return PF_ERR_NULL;
-  if (depth_pitch < plan->W || depth_pitch > INT32_MAX ||
-      (mask && (mask_pitch < plan->W || mask_pitch > INT32_MAX)))
-    return PF_ERR_PITCH;
-  auto misaligned = [](const void* q, uintptr_t m) { return (reinterpret_cast<uintptr_t>(q) & m) != 0; };
-  if (misaligned(depth, 3) || misaligned(grad_depth, 3) || (grad_normals && misaligned(grad_normals, 3)) ||
-      (grad_offsets && misaligned(grad_offsets, 3)) || (grad_residuals && misaligned(grad_residuals, 3)))
-    return PF_ERR_ALIGNMENT;
-  if (!workspace || workspace_bytes < pf_backward_workspace_bytes(plan) || misaligned(workspace, 7))
-    return PF_ERR_WORKSPACE;
-  LaunchArgs la;
-  std::memset(&la, 0, sizeof(la));
-  la.n_jobs = 1;
-  la.kappa_flag = 0.0;
-  la.kappa_fp64 = kDefaultKappaFp64;
-  la.gws = static_cast<double*>(workspace);
-  Job& jb = la.jobs[0];
-  jb.depth = depth;
-  jb.mask = mask;
-  // the backward sweep reads the upstream output gradients through the output slots
-  jb.normals = const_cast<float*>(grad_normals);
-  jb.offsets = const_cast<float*>(grad_offsets);
-  jb.residuals = const_cast<float*>(grad_residuals);
-  jb.status = nullptr;
-  jb.fx = plan->intr.fx;
-  jb.fy = plan->intr.fy;
-  jb.cx = plan->intr.cx;
-  jb.cy = plan->intr.cy;
-  jb.depth_pitch = int32_t(depth_pitch);
-  jb.mask_pitch = mask ? int32_t(mask_pitch) : 0;
-  jb.H = int32_t(plan->H);
-  jb.W = int32_t(plan->W);
-  jb.k = plan->k;
-  jb.tile_w = plan->tile_w;
-  jb.tile_h = plan->tile_h;
-  jb.n_strips = plan->n_strips;
-  jb.wg_begin = 0;
-  jb.vec_store = 0;
-  const int n_wg = plan->n_strips * plan->n_bands;
-  la.n_wg = n_wg;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const dim3 grid(static_cast<unsigned>(n_wg));
-  const dim3 block(kBlock);
-  const bool expl = plan->params.mode == PF_EXPLICIT;
-  if (expl) {
-    if (mask) hipLaunchKernelGGL((fit_planes_fused<double, PF_EXPLICIT, true, true>), grid, block, 0, s, la);
-    else hipLaunchKernelGGL((fit_planes_fused<double, PF_EXPLICIT, false, true>), grid, block, 0, s, la);
-  } else {
-    if (mask) hipLaunchKernelGGL((fit_planes_fused<double, PF_IMPLICIT, true, true>), grid, block, 0, s, la);
-    else hipLaunchKernelGGL((fit_planes_fused<double, PF_IMPLICIT, false, true>), grid, block, 0, s, la);
-  }
-  hipError_t err = hipGetLastError();
-  if (err == hipSuccess) {
-    jb.normals = grad_depth;  // second sweep writes dL/dZ through this slot
-    if (mask) hipLaunchKernelGGL((grad_depth_fused<true>), grid, block, 0, s, la);
-    else hipLaunchKernelGGL((grad_depth_fused<false>), grid, block, 0, s, la);
-    err = hipGetLastError();
-  }
-  if (err != hipSuccess) {
-    g_last_hip_error = int(err);
-    return PF_ERR_HIP;
-  }
-  return PF_OK;
+  if (!plan) return PF_ERR_NULL;
+  const pf_backward_io io = {depth, depth_pitch, mask, mask_pitch, grad_normals, grad_offsets,
+                             grad_residuals, grad_depth};
+  return pf_fit_planes_backward_batch(&plan, &io, 1, workspace, workspace_bytes, stream);
 }
 
 pf_status pf_fit_planes_xyz(const pf_plan* plan, const float* depth, int64_t depth_pitch,

@@ -184,3 +184,32 @@ def test_xyz_argument_checks_return_before_launch():
     assert call(plan, odd, 64, None, 0, fake, fake, fake, None, None) == 6
     lib.pf_plan_destroy(plan)
     lib.pf_plan_destroy(plan32)
+
+
+def test_backward_batch_argument_checks_return_before_launch():
+    from paper_2103_06644_amd._binding import _BackwardIO
+    lib = pf.load_library()
+    c1, p1 = _create(H=48, W=64, k=5, mode=0)
+    c2, p2 = _create(H=48, W=64, k=5, mode=1)
+    assert c1 == 0 and c2 == 0
+    fake = 0x10000
+    need = 2 * lib.pf_backward_workspace_bytes(p1)
+    io = (_BackwardIO * 2)(_BackwardIO(fake, 64, None, 0, None, None, None, fake),
+                           _BackwardIO(fake, 64, None, 0, None, None, None, fake))
+    same = (ctypes.c_void_p * 2)(p1.value, p1.value)
+    mixed = (ctypes.c_void_p * 2)(p1.value, p2.value)
+    ws = ctypes.c_void_p(0x20000)
+    call = lib.pf_fit_planes_backward_batch
+    assert call(same, io, 0, None, 0, None) == 0                  # empty: no-op
+    assert call(None, io, 2, ws, need, None) == 1
+    assert call(same, io, -1, ws, need, None) == 2
+    assert call(mixed, io, 2, ws, need, None) == 8                # mixed modes
+    assert call(same, io, 2, ws, need - 8, None) == 7             # workspace for one frame only
+    assert call(same, io, 2, None, need, None) == 7
+    io[1].depth_pitch = 10
+    assert call(same, io, 2, ws, need, None) == 5
+    io[1].depth_pitch = 64
+    io[1].grad_depth = None
+    assert call(same, io, 2, ws, need, None) == 1
+    lib.pf_plan_destroy(p1)
+    lib.pf_plan_destroy(p2)

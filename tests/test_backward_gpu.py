@@ -228,3 +228,38 @@ def test_backward_edge_cases(gpu):
     zt_d = torch.from_numpy(z.astype(np.float32)).to(dev)
     with pytest.raises(ValueError):
         pf.fit_planes_backward(zt_d, intr, k, torch.zeros((3, 5, 5), device=dev))
+
+
+@pytest.mark.parametrize("mode", ["implicit", "explicit"])
+def test_backward_batch_matches_single_calls(gpu, mode):
+    """Frames of mixed size, k and mask in one batched backward: bit-identical
+    to one call per frame (same kernels, same per-job arithmetic), and the
+    second group of 32 frames lands in its own launch pair."""
+    import torch
+    import paper_2103_06644_amd as pf
+    dev = torch.device("cuda:0")
+    fr = _frames()
+    specs = [(0, 0, 0, 640, 480, 9), (1, 10, 20, 300, 200, 5), (2, 100, 50, 64, 48, 15),
+             (3, 0, 0, 33, 41, 3), (0, 200, 100, 250, 120, 7)]
+    specs = (specs * 7)[:34]  # 34 frames: two launch pairs
+    depths, intrs, ks, gns, grs, masks = [], [], [], [], [], []
+    rng = np.random.Generator(np.random.PCG64(12))
+    for i, (fi, x0, y0, w, h, k) in enumerate(specs):
+        z, intr = crop(fr[fi], x0, y0, w, h)
+        depths.append(torch.from_numpy(z.astype(np.float32)).to(dev))
+        intrs.append(intr)
+        ks.append(k)
+        gns.append(torch.from_numpy(rng.standard_normal((3, h, w)).astype(np.float32)).to(dev))
+        grs.append(None if i % 3 == 0 else
+                   torch.from_numpy(rng.standard_normal((h, w)).astype(np.float32)).to(dev))
+        masks.append(None if i % 2 == 0 else
+                     torch.from_numpy((rng.random((h, w)) > 0.02).astype(np.uint8)).to(dev))
+    print("[case] backward batch", mode, len(specs), flush=True)
+    batch = pf.fit_planes_backward_batch(depths, intrs, ks, gns, None, grs, masks, mode=mode)
+    torch.cuda.synchronize()
+    for i in range(len(specs)):
+        single = pf.fit_planes_backward(depths[i], intrs[i], ks[i], gns[i], None, grs[i], masks[i],
+                                        mode=mode)
+        torch.cuda.synchronize()
+        a, b = batch[i].cpu().numpy(), single.cpu().numpy()
+        assert np.array_equal(a, b, equal_nan=True), (i, specs[i])

@@ -300,6 +300,8 @@ def cpu_baseline(frame, ks, mode, budget_s):
     z = frame.depth.astype(np.float64)
     H, W = z.shape
     threads = os.cpu_count() or 1
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        threads = max(1, min(threads, int(os.environ["OMP_NUM_THREADS"])))
     rng = np.random.Generator(np.random.PCG64(7))
     n = 2000
     total_px, total_t = 0, 0.0

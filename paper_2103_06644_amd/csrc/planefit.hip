@@ -182,6 +182,10 @@ __device__ inline float recip(float zf, float) {
   return fmaf(r, e, r);
 }
 
+// Hardware reciprocal estimate, unrefined.
+__device__ inline double rcp_raw(double x) { return __builtin_amdgcn_rcp(x); }
+__device__ inline float rcp_raw(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Reciprocal and reciprocal square root of a positive normal number: hardware
 // estimate plus Newton-Raphson refinement (two steps in FP64, one in FP32).
 __device__ inline double rcp_nr(double x) {
@@ -317,7 +321,8 @@ __device__ inline T det3(T a00, T a01, T a02, T a11, T a12, T a22) {
 }
 
 template <typename T>
-__device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22) {
+__device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22,
+                                       bool spectrum = true) {
   Eig3<T> e;
   e.degenerate = false;
   T s = fmax(fabs(c00), fmax(fabs(c11), fabs(c22)));
@@ -351,15 +356,19 @@ __device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22)
       if (!(f > T(0)) || !(fp < T(0))) break;
       const T den = T(2) * fp * fp - f * fpp;
       if (!(den > T(0))) break;
-      const T ln = l - T(2) * f * fp * rcp_nr(den);
+      // the step's reciprocal needs no refinement: an error of relative size e
+      // in a step of size s leaves e s, which the next iteration removes
+      const T ln = l - T(2) * f * fp * rcp_raw(den);
       if (!(ln > l)) break;
       const T step = ln - l;
       l = ln;
       if (step <= tol) break;
     }
   }
-  // deflate: l2 + l3 = tr - l1, l2 l3 = c1 - l1 (l2 + l3)
-  {
+  // deflate: l2 + l3 = tr - l1, l2 l3 = c1 - l1 (l2 + l3); only when the caller
+  // needs the conditioning (a uniform choice: kappa flag, FP64 fallback, adjoint)
+  e.l2 = e.l3 = T(0);
+  if (spectrum) {
     const T t = c2 - l;
     const T pr = c1 - l * t;
     const T disc = t * t - T(4) * pr;
@@ -486,7 +495,7 @@ __device__ inline Implicit3<S> implicit_matrix(const FitArgs& a, const Moments<S
 // from the smallest eigenpair e (computed in E arithmetic) of C (S arithmetic).
 template <typename S, typename E>
 __device__ inline void finish_implicit(const FitArgs& a, const Implicit3<S>& c, const Eig3<E>& e,
-                                       PixelOut& o) {
+                                       PixelOut& o, bool want_kappa) {
   S n0 = S(e.n[0]), n1 = S(e.n[1]), n2 = S(e.n[2]);
   const S gp = n0 * c.ifx, gq = n1 * c.ify, gt = n0 * c.uc + n1 * c.vc + n2;
   S d = -(gp * c.Sxw + gq * c.Syw + gt * c.Sw) * c.iS;
@@ -498,9 +507,12 @@ __device__ inline void finish_implicit(const FitArgs& a, const Implicit3<S>& c, 
   o.n2 = float(n2);
   o.d = float(d);
   o.res = sqrtf(float(fmax(S(e.l1), S(0)) * c.iN));
-  const E gap = e.l2 - e.l1;
-  o.kappa = (e.degenerate || !(gap > E(0))) ? __builtin_inff() : float(e.l3 / gap);
-  if (a.kappa_flag > 0.0 && !(o.kappa <= float(a.kappa_flag))) o.st |= 2;
+  o.kappa = 0.0f;
+  if (want_kappa) {
+    const E gap = e.l2 - e.l1;
+    o.kappa = (e.degenerate || !(gap > E(0))) ? __builtin_inff() : float(e.l3 / gap);
+    if (a.kappa_flag > 0.0 && !(o.kappa <= float(a.kappa_flag))) o.st |= 2;
+  }
 }
 
 template <typename S, int MODE>
@@ -525,7 +537,9 @@ __device__ inline PixelOut solve_moments(const FitArgs& a, const Moments<S>& m, 
     o.res = inv * sqrtf(fmaxf(float(m.SSR), 0.0f) * float(a.inv_N));
   } else {
     const Implicit3<S> c = implicit_matrix<S>(a, m, uc, vc);
-    finish_implicit<S, S>(a, c, smallest_eig<S>(c.c00, c.c01, c.c02, c.c11, c.c12, c.c22), o);
+    const bool flag = a.kappa_flag > 0.0;
+    finish_implicit<S, S>(a, c, smallest_eig<S>(c.c00, c.c01, c.c02, c.c11, c.c12, c.c22, flag),
+                          o, flag);
   }
   return o;
 }
@@ -579,11 +593,12 @@ __device__ inline PixelOut solve_pixel_df(const FitArgs& a, df32 B, df32 Sxw, df
   o.st = 0;
   const Eig3<float> ef = smallest_eig<float>(float(c.c00), float(c.c01), float(c.c02),
                                              float(c.c11), float(c.c12), float(c.c22));
-  finish_implicit<double, float>(a, c, ef, o);
+  finish_implicit<double, float>(a, c, ef, o, true);
   if (!(o.kappa <= float(a.kappa_fp64))) {
     o.st = 4;
+    const bool flag = a.kappa_flag > 0.0;
     finish_implicit<double, double>(a, c, smallest_eig<double>(c.c00, c.c01, c.c02, c.c11,
-                                                               c.c12, c.c22), o);
+                                                               c.c12, c.c22, flag), o, flag);
   }
   return o;
 }
@@ -1301,7 +1316,8 @@ __global__ __launch_bounds__(kBlock) void fit_planes_xyz(LaunchArgs la) {
           double n0, n1, n2, d, res;
           st = 0;
           if (MODE == PF_IMPLICIT) {
-            const Eig3<double> e = smallest_eig<double>(cxx, cxy, cxz, cyy, cyz, czz);
+            const Eig3<double> e =
+                smallest_eig<double>(cxx, cxy, cxz, cyy, cyz, czz, la.kappa_flag > 0.0);
             n0 = e.n[0]; n1 = e.n[1]; n2 = e.n[2];
             d = -(n0 * Mx + n1 * My + n2 * Mz);
             res = sqrt(fmax(e.l1, 0.0) * iN);

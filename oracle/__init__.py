@@ -46,6 +46,10 @@ def _load():
     lib.pfo_fit_points.argtypes = [_dp, i64, i64, _u8p, d, d, d, d, i32, i32, _i64p, _i64p,
                                    i64, i32, _dp, _dp, _dp, _dp, _u8p]
     lib.pfo_fit_points.restype = ctypes.c_int
+    lib.pfo_fit_rects.argtypes = [_dp, i64, i64, _u8p, d, d, d, d,
+                                  ctypes.POINTER(ctypes.c_int32), i64, i32, i32, _dp, _dp, _dp,
+                                  _dp, _u8p]
+    lib.pfo_fit_rects.restype = ctypes.c_int
     lib.pfo_camera_moments.argtypes = [d, d, d, d, i32, i64, i64, _dp]
     lib.pfo_camera_moments.restype = None
     lib.pfo_window_sums.argtypes = [_dp, i64, i64, _u8p, d, d, d, d, i32, _dp]
@@ -137,6 +141,25 @@ def fit_points(depth, intrinsics, k, xs, ys, mode="implicit", mask=None, threads
                                 _ptr(out["normals"]), _ptr(out["offsets"]),
                                 _ptr(out["residuals"]), _ptr(out["kappa"]),
                                 _ptr(out["status"], _u8p))
+    if rc != 0:
+        raise ValueError("oracle: bad arguments")
+    return out
+
+
+def fit_rects(depth, intrinsics, rects, mode="implicit", mask=None, threads=0):
+    """Fits to rectangles rects [n, 4] = (x0, y0, w, h); arrays of length n."""
+    depth, mask = _prep(depth, mask)
+    H, W = depth.shape
+    rects = np.ascontiguousarray(rects, dtype=np.int32).reshape(-1, 4)
+    n = rects.shape[0]
+    fx, fy, cx, cy = map(float, intrinsics)
+    out = dict(normals=np.empty((3, n)), offsets=np.empty(n), residuals=np.empty(n),
+               kappa=np.empty(n), status=np.empty(n, np.uint8))
+    rc = _load().pfo_fit_rects(_ptr(depth), H, W, _ptr(mask, _u8p), fx, fy, cx, cy,
+                               rects.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n,
+                               _mode(mode), int(threads), _ptr(out["normals"]),
+                               _ptr(out["offsets"]), _ptr(out["residuals"]),
+                               _ptr(out["kappa"]), _ptr(out["status"], _u8p))
     if rc != 0:
         raise ValueError("oracle: bad arguments")
     return out

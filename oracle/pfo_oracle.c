@@ -83,13 +83,14 @@ static int pixel_valid(const double* depth, const uint8_t* mask, int64_t idx) {
 
 /* Back-projected points of the window centred at (x0, y0); returns the number
  * of points, or -1 if any window pixel is outside the image or invalid. */
-static int gather_window(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
-                         const cam_t* cam, int k, int64_t x0, int64_t y0, double* X,
-                         double* Y, double* Z) {
-  int r = k / 2, n = 0;
-  for (int dy = -r; dy <= r; ++dy)
-    for (int dx = -r; dx <= r; ++dx) {
-      int64_t x = x0 + dx, y = y0 + dy;
+/* Back-projects (Eq. 1) the w x h pixels of columns xa .. xa+w-1 and rows
+ * ya .. ya+h-1; -1 if any lies outside the image or is invalid. */
+static int gather_rect(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
+                       const cam_t* cam, int64_t xa, int64_t ya, int64_t w, int64_t h,
+                       double* X, double* Y, double* Z) {
+  int n = 0;
+  for (int64_t y = ya; y < ya + h; ++y)
+    for (int64_t x = xa; x < xa + w; ++x) {
       if (x < 0 || y < 0 || x >= W || y >= H) return -1;
       int64_t idx = y * W + x;
       if (!pixel_valid(depth, mask, idx)) return -1;
@@ -100,6 +101,13 @@ static int gather_window(const double* depth, int64_t H, int64_t W, const uint8_
       ++n;
     }
   return n;
+}
+
+static int gather_window(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
+                         const cam_t* cam, int k, int64_t x0, int64_t y0, double* X,
+                         double* Y, double* Z) {
+  const int r = k / 2;
+  return gather_rect(depth, H, W, mask, cam, x0 - r, y0 - r, k, k, X, Y, Z);
 }
 
 typedef struct {
@@ -278,12 +286,22 @@ static void nan_out(int64_t o, int64_t plane, double* normals, double* offsets,
   if (status) status[o] = 1;
 }
 
+static void fit_gathered(const double* X, const double* Y, const double* Z, int N, int mode,
+                         int64_t o, int64_t plane, double* normals, double* offsets,
+                         double* residuals, double* kappa, uint8_t* status);
+
 static void fit_one(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
                     const cam_t* cam, int k, int mode, int64_t x0, int64_t y0, int64_t o,
                     int64_t plane, double* normals, double* offsets, double* residuals,
                     double* kappa, uint8_t* status, double* buf) {
   double *X = buf, *Y = buf + k * k, *Z = buf + 2 * k * k;
   int N = gather_window(depth, H, W, mask, cam, k, x0, y0, X, Y, Z);
+  fit_gathered(X, Y, Z, N, mode, o, plane, normals, offsets, residuals, kappa, status);
+}
+
+static void fit_gathered(const double* X, const double* Y, const double* Z, int N, int mode,
+                         int64_t o, int64_t plane, double* normals, double* offsets,
+                         double* residuals, double* kappa, uint8_t* status) {
   if (N < 0) {
     nan_out(o, plane, normals, offsets, residuals, kappa, status);
     return;
@@ -358,6 +376,35 @@ int pfo_fit_points(const double* depth, int64_t H, int64_t W, const uint8_t* mas
     for (int64_t i = 0; i < count; ++i)
       fit_one(depth, H, W, mask, &cam, k, mode, xs[i], ys[i], i, count, normals, offsets,
               residuals, kappa, status, buf);
+    free(buf);
+  }
+  return 0;
+}
+
+int pfo_fit_rects(const double* depth, int64_t H, int64_t W, const uint8_t* mask, double fx,
+                  double fy, double cx, double cy, const int32_t* rects, int64_t count,
+                  int32_t mode, int32_t threads, double* normals, double* offsets,
+                  double* residuals, double* kappa, uint8_t* status) {
+  if (!depth || !rects || !normals || !offsets || !residuals || count < 0 || H <= 0 ||
+      W <= 0 || mode < 0 || mode > 5)
+    return -1;
+  cam_t cam = {fx, fy, cx, cy};
+#ifdef _OPENMP
+  int nt = threads > 0 ? threads : omp_get_max_threads();
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 16)
+#endif
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t xa = rects[4 * i], ya = rects[4 * i + 1];
+    const int64_t w = rects[4 * i + 2], h = rects[4 * i + 3];
+    int N = -1;
+    double* buf = NULL;
+    if (w >= 2 && h >= 2 && xa >= 0 && ya >= 0 && xa + w <= W && ya + h <= H) {
+      buf = (double*)malloc(sizeof(double) * 3 * (size_t)(w * h));
+      N = gather_rect(depth, H, W, mask, &cam, xa, ya, w, h, buf, buf + w * h,
+                      buf + 2 * w * h);
+    }
+    fit_gathered(buf, buf ? buf + w * h : NULL, buf ? buf + 2 * w * h : NULL, N, mode, i, count,
+                 normals, offsets, residuals, kappa, status);
     free(buf);
   }
   return 0;

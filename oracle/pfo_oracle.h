@@ -69,6 +69,17 @@ int pfo_fit_points(const double* depth, int64_t H, int64_t W, const uint8_t* mas
                    double* normals, double* offsets, double* residuals, double* kappa,
                    uint8_t* status);
 
+/* Fits to arbitrary rectangles, the use of integral images the paper makes
+ * (Sec. II-C): rects is int32 [count][4] = (x0, y0, w, h), covering columns
+ * x0 .. x0+w-1 and rows y0 .. y0+h-1.  A rectangle is valid iff w, h >= 2, it
+ * lies in the image and all its pixels are valid; the fit, orientation,
+ * residual and kappa follow the window fits.  Outputs are [count]
+ * (normals [3][count]). */
+int pfo_fit_rects(const double* depth, int64_t H, int64_t W, const uint8_t* mask, double fx,
+                  double fy, double cx, double cy, const int32_t* rects, int64_t count,
+                  int32_t mode, int32_t threads, double* normals, double* offsets,
+                  double* residuals, double* kappa, uint8_t* status);
+
 /* Brute-force window sums of the camera-only monomial products over the
  * window centred at (x0, y0): [sum u^2, sum u v, sum u, sum v^2, sum v, N]
  * with u = (x - cx)/fx, v = (y - cy)/fy (Eq. 10).  No image bounds apply. */

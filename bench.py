@@ -292,6 +292,53 @@ def xyz_measure(torch, pf, frames_for):
     return res
 
 
+def rects_measure(torch, pf, np, frames_for):
+    """Fits to many rectangles of one 1080p frame (the paper's use of integral
+    images, Sec. II-C): the FP64 integral images of the frame (four launches),
+    then 100,000 seeded rectangles of 8..128 pixels a side, implicit and
+    explicit; each timed over graph replays."""
+    f = frames_for("hd_1920x1080")[0]
+    H, W = f.depth.shape
+    d = torch.from_numpy(f.depth).cuda()
+    rng = np.random.Generator(np.random.PCG64(31))
+    n = 100_000
+    w = rng.integers(8, 129, n)
+    h = rng.integers(8, 129, n)
+    rects = np.stack([rng.integers(0, W - w + 1), rng.integers(0, H - h + 1), w, h], 1)
+    r = torch.from_numpy(rects.astype(np.int32)).cuda()
+    res = {"frame": "hd_1920x1080", "rects": n, "sides": "8..128"}
+    for mode in ("implicit", "explicit"):
+        ws = pf.integral_images(d, f.intrinsics, mode=mode)
+        out = pf.fit_rects(ws, d.shape, f.intrinsics, r, mode=mode)
+        for name, fn in (("integral", lambda: pf.integral_images(d, f.intrinsics, mode=mode,
+                                                                 workspace=ws)),
+                         ("rects", lambda: pf.fit_rects(ws, d.shape, f.intrinsics, r, mode=mode,
+                                                        out=out))):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=side):
+                    for _ in range(10):
+                        fn()
+            torch.cuda.current_stream().wait_stream(side)
+            g.replay()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(5):
+                g.replay()
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / 50
+            res[f"{mode}_{name}_ms"] = round(ms, 5)
+        res[f"{mode}_Mrects_s"] = round(n / (res[f"{mode}_rects_ms"] * 1e-3) / 1e6, 1)
+    return res
+
+
 def cpu_baseline(frame, ks, mode, budget_s):
     """The FP64 oracle on the host: random sample of window centres, growing until
     about budget_s seconds of work; returns Mpixel/s and what was sampled."""
@@ -393,6 +440,7 @@ def main():
         extras["batch_mixed_64"] = batch_measure(torch, pf, np, frames_for)
         extras["diff_8x640x480"] = diff_measure(torch, pf, np, frames_for, diff_loss_inputs)
         extras["xyz_vs_rgbd"] = xyz_measure(torch, pf, frames_for)
+        extras["rects_1080p"] = rects_measure(torch, pf, np, frames_for)
         out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(f, ks, "implicit", args.cpu_seconds)

@@ -228,6 +228,34 @@ pf_status pf_fit_planes_xyz(const pf_plan* plan, const float* depth, int64_t dep
                             const uint8_t* mask, int64_t mask_pitch, float* normals,
                             float* offsets, float* residuals, uint8_t* status, void* stream);
 
+/* Fits to arbitrary rectangles of one frame: the paper's own use of integral
+ * images (Sec. II-C), for many fits to regions of a frame (tiles, quadtree
+ * cells, segmentation candidates) instead of one per pixel.
+ *
+ * pf_integral_images builds, in FP64 on the GPU, the integral images of the
+ * four depth-dependent moments of Eq. 14 (centred on the frame's reference
+ * disparity) and of the valid count into the caller's workspace (4 small
+ * launches).  pf_fit_rects then fits one plane per rectangle from the four
+ * corners of each image; the camera-only moments of a w x h rectangle are in
+ * closed form (Sec. II-A/B).  Mode (implicit / explicit), kappa_flag and the
+ * camera come from the plan; its window is not used; arithmetic is FP64.
+ *   workspace  device, >= pf_integral_workspace_bytes(plan), 8-byte aligned;
+ *              written by pf_integral_images, read by pf_fit_rects
+ *   rects      device int32 [n][4] = (x0, y0, w, h): columns x0 .. x0+w-1,
+ *              rows y0 .. y0+h-1
+ *   normals    device float [3][n]; offsets, residuals float [n]; status
+ *              uint8 [n] or NULL
+ * A rectangle is valid iff w, h >= 2, it lies in the image and every pixel in
+ * it is valid; other rectangles get NaN outputs and status bit 0 (not an
+ * error).  Outputs follow pf_fit_planes (orientation, residual, status bit 1). */
+size_t pf_integral_workspace_bytes(const pf_plan* plan);
+pf_status pf_integral_images(const pf_plan* plan, const float* depth, int64_t depth_pitch,
+                             const uint8_t* mask, int64_t mask_pitch, void* workspace,
+                             size_t workspace_bytes, void* stream);
+pf_status pf_fit_rects(const pf_plan* plan, const void* workspace, const int32_t* rects,
+                       int64_t n, float* normals, float* offsets, float* residuals,
+                       uint8_t* status, void* stream);
+
 /* Static description of a status code. */
 const char* pf_status_string(pf_status s);
 

@@ -72,6 +72,7 @@ EXPORTS = ("pf_plan_create", "pf_plan_destroy", "pf_plan_workspace_bytes",
            "pf_plan_camera_moments", "pf_fit_planes", "pf_fit_planes_batch",
            "pf_backward_workspace_bytes", "pf_fit_planes_backward",
            "pf_fit_planes_backward_batch", "pf_fit_planes_xyz",
+           "pf_integral_workspace_bytes", "pf_integral_images", "pf_fit_rects",
            "pf_status_string", "pf_last_hip_error")
 
 
@@ -110,6 +111,12 @@ def load_library(path: str | None = None):
                                                      ctypes.POINTER(_BackwardIO), i32, vp,
                                                      ctypes.c_size_t, vp]
         lib.pf_fit_planes_backward_batch.restype = i32
+        lib.pf_integral_workspace_bytes.argtypes = [vp]
+        lib.pf_integral_workspace_bytes.restype = ctypes.c_size_t
+        lib.pf_integral_images.argtypes = [vp, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
+        lib.pf_integral_images.restype = i32
+        lib.pf_fit_rects.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp]
+        lib.pf_fit_rects.restype = i32
         lib.pf_fit_planes_xyz.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp]
         lib.pf_fit_planes_xyz.restype = i32
         lib.pf_status_string.argtypes = [i32]
@@ -310,6 +317,59 @@ def fit_planes_xyz(depth, intrinsics, window: int, valid_mask=None, *, mode: str
             _stream_handle(torch, dev, stream))
     _check(code)
     return normals, offsets, residuals, status
+
+
+def integral_images(depth, intrinsics, valid_mask=None, *, mode="implicit", kappa_flag=0.0,
+                    workspace=None, stream=None):
+    """FP64 integral images of one frame on the GPU (Sec. II-C), for
+    fit_rects.  Returns the workspace tensor that holds them."""
+    import torch
+    _check_depth(torch, depth)
+    H, W = depth.shape
+    dev = depth.device
+    plan = get_plan(intrinsics, H, W, 3 if min(H, W) >= 3 else 1, mode, "fp64", kappa_flag)
+    need = int(plan._lib.pf_integral_workspace_bytes(plan.handle))
+    if workspace is None or workspace.numel() * workspace.element_size() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    mptr, mpitch = _mask_arg(torch, valid_mask, depth)
+    with _on_device(torch, dev):
+        code = plan._lib.pf_integral_images(
+            plan.handle, ctypes.c_void_p(depth.data_ptr()), depth.stride(0),
+            ctypes.c_void_p(mptr) if mptr else None, mpitch,
+            ctypes.c_void_p(workspace.data_ptr()), need, _stream_handle(torch, dev, stream))
+    _check(code)
+    return workspace
+
+
+def fit_rects(workspace, frame_shape, intrinsics, rects, *, mode="implicit", kappa_flag=0.0,
+              out=None, stream=None):
+    """Plane fits to rectangles rects (int32 [n, 4] = x0, y0, w, h, on the
+    device) from the integral images in `workspace` (see integral_images).
+    Returns (normals [3, n], offsets [n], residuals [n], status [n])."""
+    import torch
+    H, W = (int(v) for v in frame_shape)
+    dev = workspace.device
+    if rects.dtype != torch.int32 or rects.dim() != 2 or rects.shape[1] != 4 or \
+            not rects.is_contiguous() or rects.device != dev:
+        raise ValueError("rects must be a contiguous int32 [n, 4] tensor on the workspace's device")
+    n = rects.shape[0]
+    plan = get_plan(intrinsics, H, W, 3 if min(H, W) >= 3 else 1, mode, "fp64", kappa_flag)
+    if out is None:
+        out = (torch.empty((3, n), dtype=torch.float32, device=dev),
+               torch.empty(n, dtype=torch.float32, device=dev),
+               torch.empty(n, dtype=torch.float32, device=dev),
+               torch.empty(n, dtype=torch.uint8, device=dev))
+    normals, offsets, residuals, status = out
+    if n == 0:
+        return out
+    with _on_device(torch, dev):
+        code = plan._lib.pf_fit_rects(
+            plan.handle, ctypes.c_void_p(workspace.data_ptr()), ctypes.c_void_p(rects.data_ptr()),
+            n, ctypes.c_void_p(normals.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+            ctypes.c_void_p(residuals.data_ptr()), ctypes.c_void_p(status.data_ptr()),
+            _stream_handle(torch, dev, stream))
+    _check(code)
+    return out
 
 
 def _check_depth(torch, depth):

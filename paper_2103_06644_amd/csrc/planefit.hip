@@ -1356,6 +1356,260 @@ __global__ __launch_bounds__(kBlock) void fit_planes_xyz(LaunchArgs la) {
 }
 
 // ---------------------------------------------------------------------------
+// Global integral images and fits to arbitrary rectangles: the paper's own use
+// of integral images (Sec. II-C), for fits to many regions of one frame (tiles,
+// segmentation candidates) rather than to every pixel's window.
+//
+// Workspace: a 256-byte header (the frame's reference disparity w_ref at [0]),
+// then five FP64 planes I[c][H+1][W+1] with a zero first row and column,
+//   c = 0: w^ = w - w_ref,  1: x~ w^,  2: y~ w^,  3: w^2,  4: valid count,
+// summed over valid pixels, with x~ = x - W/2 and y~ = y - H/2 (integers; the
+// centring halves the magnitude of the prefix sums a corner difference cancels),
+// then the column
+// totals of each band of kIntBand rows (5 [n_bands][W+1] planes).
+// ---------------------------------------------------------------------------
+constexpr int kIntBand = 16;
+constexpr int64_t kIntHeader = 32;  // doubles (256 bytes)
+
+struct IntegralArgs {
+  const float* depth;
+  const uint8_t* mask;
+  int64_t depth_pitch, mask_pitch;
+  int32_t H, W;
+  double* ws;
+};
+
+__device__ inline int64_t int_plane(const IntegralArgs& ia) {
+  return int64_t(ia.H + 1) * (ia.W + 1);
+}
+
+__device__ inline float int_load(const IntegralArgs& ia, int x, int y) {
+  float z = ia.depth[int64_t(y) * ia.depth_pitch + x];
+  if (ia.mask && ia.mask[int64_t(y) * ia.mask_pitch + x] == 0) z = 0.0f;
+  return z;
+}
+
+// the frame's reference disparity: mean valid w of the middle row (one workgroup)
+__global__ __launch_bounds__(kBlock) void integral_ref(IntegralArgs ia) {
+  __shared__ double red[2 * (kBlock / 64)];
+  const int tid = threadIdx.x, y = ia.H / 2;
+  double s = 0.0, c = 0.0;
+  for (int x = tid; x < ia.W; x += kBlock) {
+    const float z = int_load(ia, x, y);
+    if (depth_valid(z)) {
+      s += 1.0 / double(z);
+      c += 1.0;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_down(s, off, 64);
+    c += __shfl_down(c, off, 64);
+  }
+  if ((tid & 63) == 0) {
+    red[2 * (tid >> 6)] = s;
+    red[2 * (tid >> 6) + 1] = c;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double ts = 0.0, tc = 0.0;
+    for (int i = 0; i < kBlock / 64; ++i) {
+      ts += red[2 * i];
+      tc += red[2 * i + 1];
+    }
+    ia.ws[0] = tc > 0.0 ? ts / tc : 0.0;
+  }
+}
+
+// row prefix sums: one workgroup per image row, 256-column tiles, wave scans
+__global__ __launch_bounds__(kBlock) void integral_rows(IntegralArgs ia) {
+  __shared__ double tot[kBlock / 64][5];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int y = int(blockIdx.x);
+  const int64_t P = int_plane(ia), ld = ia.W + 1;
+  double* I = ia.ws + kIntHeader;
+  const double wref = ia.ws[0];
+  if (tid == 0)
+    for (int c = 0; c < 5; ++c) I[c * P + int64_t(y + 1) * ld] = 0.0;
+  if (y == 0)
+    for (int x = tid; x <= ia.W; x += kBlock)
+      for (int c = 0; c < 5; ++c) I[c * P + x] = 0.0;
+  double carry[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int base = 0; base < ia.W; base += kBlock) {
+    const int x = base + tid;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (x < ia.W) {
+      const float z = int_load(ia, x, y);
+      if (depth_valid(z)) {
+        const double wh = 1.0 / double(z) - wref;
+        v[0] = wh;
+        v[1] = double(x - ia.W / 2) * wh;
+        v[2] = double(y - ia.H / 2) * wh;
+        v[3] = wh * wh;
+        v[4] = 1.0;
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const double o = __shfl_up(v[c], off, 64);
+        if (lane >= off) v[c] += o;
+      }
+    }
+    if (lane == 63)
+      for (int c = 0; c < 5; ++c) tot[wave][c] = v[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      double before = 0.0, all = 0.0;
+      for (int i = 0; i < kBlock / 64; ++i) {
+        if (i < wave) before += tot[i][c];
+        all += tot[i][c];
+      }
+      if (x < ia.W) I[c * P + int64_t(y + 1) * ld + x + 1] = carry[c] + before + v[c];
+      carry[c] += all;
+    }
+    __syncthreads();
+  }
+}
+
+// column totals of every band of kIntBand rows (rows 1 .. H of the planes)
+__global__ __launch_bounds__(kBlock) void integral_band_totals(IntegralArgs ia) {
+  const int x = int(blockIdx.x) * kBlock + threadIdx.x;
+  const int band = int(blockIdx.y);
+  if (x > ia.W) return;
+  const int64_t P = int_plane(ia), ld = ia.W + 1;
+  const int n_bands = (ia.H + kIntBand - 1) / kIntBand;
+  const double* I = ia.ws + kIntHeader;
+  double* T = ia.ws + kIntHeader + 5 * P;
+  const int y0 = 1 + band * kIntBand, y1 = min(y0 + kIntBand, ia.H + 1);
+  for (int c = 0; c < 5; ++c) {
+    double s = 0.0;
+    for (int yy = y0; yy < y1; ++yy) s += I[c * P + int64_t(yy) * ld + x];
+    T[(int64_t(c) * n_bands + band) * ld + x] = s;
+  }
+}
+
+// column prefix sums within each band, started from the totals of the bands above
+__global__ __launch_bounds__(kBlock) void integral_cols(IntegralArgs ia) {
+  const int x = int(blockIdx.x) * kBlock + threadIdx.x;
+  const int band = int(blockIdx.y);
+  if (x > ia.W) return;
+  const int64_t P = int_plane(ia), ld = ia.W + 1;
+  const int n_bands = (ia.H + kIntBand - 1) / kIntBand;
+  double* I = ia.ws + kIntHeader;
+  const double* T = ia.ws + kIntHeader + 5 * P;
+  const int y0 = 1 + band * kIntBand, y1 = min(y0 + kIntBand, ia.H + 1);
+  for (int c = 0; c < 5; ++c) {
+    double acc = 0.0;
+    for (int b = 0; b < band; ++b) acc += T[(int64_t(c) * n_bands + b) * ld + x];
+    double v[kIntBand];
+#pragma unroll
+    for (int j = 0; j < kIntBand; ++j)
+      v[j] = (y0 + j < y1) ? I[c * P + int64_t(y0 + j) * ld + x] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kIntBand; ++j) {
+      acc += v[j];
+      if (y0 + j < y1) I[c * P + int64_t(y0 + j) * ld + x] = acc;
+    }
+  }
+}
+
+struct RectArgs {
+  const double* ws;
+  const int32_t* rects;  // [n][4] = x0, y0, w, h
+  float* normals;        // [3][n]
+  float* offsets;
+  float* residuals;
+  uint8_t* status;
+  int64_t n;
+  int32_t H, W;
+  double fx, fy, cx, cy;
+  double kappa_flag;
+};
+
+// One fit per rectangle from the four corners of each integral image.  The
+// camera-only moments of a w x h rectangle, centred on (xc, yc) =
+// (x0 + (w-1)/2, y0 + (h-1)/2), are diagonal: sum x'^2 = h w (w^2-1)/12,
+// sum y'^2 = w h (h^2-1)/12, N = w h; the rest is the per-pixel solve with
+// unequal x and y second moments.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void fit_rects_kernel(RectArgs ra) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= ra.n) return;
+  const int x0 = ra.rects[4 * i], y0 = ra.rects[4 * i + 1];
+  const int w = ra.rects[4 * i + 2], h = ra.rects[4 * i + 3];
+  float on0 = __builtin_nanf(""), on1 = on0, on2 = on0, od = on0, ores = on0;
+  uint8_t st = 1;
+  const bool inside = w >= 2 && h >= 2 && x0 >= 0 && y0 >= 0 && x0 <= ra.W - w &&
+                      y0 <= ra.H - h;
+  if (inside) {
+    const int64_t ld = ra.W + 1, P = int64_t(ra.H + 1) * ld;
+    const double* I = ra.ws + kIntHeader;
+    const int64_t a = int64_t(y0) * ld + x0, b = a + w, c = a + int64_t(h) * ld, d = c + w;
+    double S[5];
+#pragma unroll
+    for (int ch = 0; ch < 5; ++ch)
+      S[ch] = (I[ch * P + d] - I[ch * P + b]) - (I[ch * P + c] - I[ch * P + a]);
+    const double N = double(w) * double(h);
+    if (S[4] == N) {
+      const double wref = ra.ws[0];
+      const double xc = x0 + 0.5 * (w - 1), yc = y0 + 0.5 * (h - 1);
+      const double B = S[0], Q = S[3];
+      const double Sxw = S[1] - (xc - ra.W / 2) * B, Syw = S[2] - (yc - ra.H / 2) * B;
+      const double S2x = N * (double(w) * w - 1.0) / 12.0, S2y = N * (double(h) * h - 1.0) / 12.0;
+      const double V = N * Q - B * B;
+      const double Sw = N * wref + B;
+      const double Sww = Q + wref * (2.0 * B + N * wref);
+      const double uc = (xc - ra.cx) / ra.fx, vc = (yc - ra.cy) / ra.fy;
+      double n0, n1, n2, dd, res;
+      st = 0;
+      if (MODE == PF_EXPLICIT) {
+        const double ax = ra.fx * Sxw / S2x, ay = ra.fy * Syw / S2y;
+        const double az = Sw / N - ax * uc - ay * vc;
+        const double rho = sqrt(ax * ax + ay * ay + az * az);
+        n0 = -ax / rho; n1 = -ay / rho; n2 = -az / rho;
+        dd = 1.0 / rho;
+        const double ssr = fmax(V / N - Sxw * Sxw / S2x - Syw * Syw / S2y, 0.0);
+        res = dd * sqrt(ssr / N);
+      } else {
+        // C = M^T G M, G = diag(S2x, S2y, N) - g g^T / Sww (G33 = V / Sww)
+        const double iS = 1.0 / Sww, ifx = 1.0 / ra.fx, ify = 1.0 / ra.fy;
+        const double g11 = S2x - Sxw * Sxw * iS, g22 = S2y - Syw * Syw * iS;
+        const double g12 = -Sxw * Syw * iS, g13 = -Sxw * Sw * iS, g23 = -Syw * Sw * iS;
+        const double g33 = V * iS;
+        const double c00 = g11 * ifx * ifx + 2.0 * g13 * uc * ifx + g33 * uc * uc;
+        const double c01 = g12 * ifx * ify + g13 * vc * ifx + g23 * uc * ify + g33 * uc * vc;
+        const double c02 = g13 * ifx + g33 * uc;
+        const double c11 = g22 * ify * ify + 2.0 * g23 * vc * ify + g33 * vc * vc;
+        const double c12 = g23 * ify + g33 * vc;
+        const double c22 = g33;
+        const bool flag = ra.kappa_flag > 0.0;
+        const Eig3<double> e = smallest_eig<double>(c00, c01, c02, c11, c12, c22, flag);
+        n0 = e.n[0]; n1 = e.n[1]; n2 = e.n[2];
+        dd = -(n0 * ifx * Sxw + n1 * ify * Syw + (n0 * uc + n1 * vc + n2) * Sw) * iS;
+        res = sqrt(fmax(e.l1, 0.0) / N);
+        if (flag) {
+          const double gap = e.l2 - e.l1;
+          const double kap = (e.degenerate || !(gap > 0.0)) ? __builtin_inf() : e.l3 / gap;
+          if (!(kap <= ra.kappa_flag)) st = 2;
+        }
+      }
+      if (dd < 0.0) {
+        dd = -dd; n0 = -n0; n1 = -n1; n2 = -n2;
+      }
+      on0 = float(n0); on1 = float(n1); on2 = float(n2); od = float(dd); ores = float(res);
+    }
+  }
+  ra.normals[i] = on0;
+  ra.normals[ra.n + i] = on1;
+  ra.normals[2 * ra.n + i] = on2;
+  ra.offsets[i] = od;
+  ra.residuals[i] = ores;
+  if (ra.status) ra.status[i] = st;
+}
+
+// ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
 thread_local int g_last_hip_error = 0;
@@ -1729,6 +1983,87 @@ pf_status pf_fit_planes_xyz(const pf_plan* plan, const float* depth, int64_t dep
     if (mask) hipLaunchKernelGGL((fit_planes_xyz<PF_IMPLICIT, true>), grid, block, 0, s, la);
     else hipLaunchKernelGGL((fit_planes_xyz<PF_IMPLICIT, false>), grid, block, 0, s, la);
   }
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess) {
+    g_last_hip_error = int(err);
+    return PF_ERR_HIP;
+  }
+  return PF_OK;
+}
+
+size_t pf_integral_workspace_bytes(const pf_plan* plan) {
+  if (!plan) return 0;
+  const size_t ld = size_t(plan->W) + 1, P = (size_t(plan->H) + 1) * ld;
+  const size_t bands = (size_t(plan->H) + kIntBand - 1) / kIntBand;
+  return sizeof(double) * (size_t(kIntHeader) + 5 * P + 5 * bands * ld);
+}
+
+pf_status pf_integral_images(const pf_plan* plan, const float* depth, int64_t depth_pitch,
+                             const uint8_t* mask, int64_t mask_pitch, void* workspace,
+                             size_t workspace_bytes, void* stream) {
+  if (!plan || !depth) return PF_ERR_NULL;
+  if (depth_pitch < plan->W || (mask && mask_pitch < plan->W)) return PF_ERR_PITCH;
+  if ((reinterpret_cast<uintptr_t>(depth) & 3) != 0) return PF_ERR_ALIGNMENT;
+  if (!workspace || workspace_bytes < pf_integral_workspace_bytes(plan) ||
+      (reinterpret_cast<uintptr_t>(workspace) & 7) != 0)
+    return PF_ERR_WORKSPACE;
+  IntegralArgs ia;
+  ia.depth = depth;
+  ia.mask = mask;
+  ia.depth_pitch = depth_pitch;
+  ia.mask_pitch = mask ? mask_pitch : 0;
+  ia.H = int32_t(plan->H);
+  ia.W = int32_t(plan->W);
+  ia.ws = static_cast<double*>(workspace);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const dim3 block(kBlock);
+  const unsigned strips = unsigned((plan->W + 1 + kBlock - 1) / kBlock);
+  const unsigned bands = unsigned((plan->H + kIntBand - 1) / kIntBand);
+  hipLaunchKernelGGL(integral_ref, dim3(1), block, 0, s, ia);
+  hipLaunchKernelGGL(integral_rows, dim3(unsigned(plan->H)), block, 0, s, ia);
+  hipLaunchKernelGGL(integral_band_totals, dim3(strips, bands), block, 0, s, ia);
+  hipLaunchKernelGGL(integral_cols, dim3(strips, bands), block, 0, s, ia);
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess) {
+    g_last_hip_error = int(err);
+    return PF_ERR_HIP;
+  }
+  return PF_OK;
+}
+
+pf_status pf_fit_rects(const pf_plan* plan, const void* workspace, const int32_t* rects,
+                       int64_t n, float* normals, float* offsets, float* residuals,
+                       uint8_t* status, void* stream) {
+  if (n < 0) return PF_ERR_SHAPE;
+  if (n == 0) return PF_OK;
+  if (!plan || !workspace || !rects || !normals || !offsets || !residuals) return PF_ERR_NULL;
+  if (n > int64_t(INT32_MAX) * kBlock / 4) return PF_ERR_SHAPE;
+  auto misaligned = [](const void* q, uintptr_t m) { return (reinterpret_cast<uintptr_t>(q) & m) != 0; };
+  if (misaligned(rects, 3) || misaligned(normals, 3) || misaligned(offsets, 3) ||
+      misaligned(residuals, 3))
+    return PF_ERR_ALIGNMENT;
+  if (misaligned(workspace, 7)) return PF_ERR_WORKSPACE;
+  RectArgs ra;
+  ra.ws = static_cast<const double*>(workspace);
+  ra.rects = rects;
+  ra.normals = normals;
+  ra.offsets = offsets;
+  ra.residuals = residuals;
+  ra.status = status;
+  ra.n = n;
+  ra.H = int32_t(plan->H);
+  ra.W = int32_t(plan->W);
+  ra.fx = plan->intr.fx;
+  ra.fy = plan->intr.fy;
+  ra.cx = plan->intr.cx;
+  ra.cy = plan->intr.cy;
+  ra.kappa_flag = plan->params.kappa_flag;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const dim3 grid(unsigned((n + kBlock - 1) / kBlock)), block(kBlock);
+  if (plan->params.mode == PF_EXPLICIT)
+    hipLaunchKernelGGL((fit_rects_kernel<PF_EXPLICIT>), grid, block, 0, s, ra);
+  else
+    hipLaunchKernelGGL((fit_rects_kernel<PF_IMPLICIT>), grid, block, 0, s, ra);
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess) {
     g_last_hip_error = int(err);

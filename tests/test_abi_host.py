@@ -213,3 +213,23 @@ def test_backward_batch_argument_checks_return_before_launch():
     assert call(same, io, 2, ws, need, None) == 1
     lib.pf_plan_destroy(p1)
     lib.pf_plan_destroy(p2)
+
+
+def test_rect_argument_checks_return_before_launch():
+    lib = pf.load_library()
+    code, plan = _create(H=48, W=64, k=5)
+    assert code == 0
+    need = lib.pf_integral_workspace_bytes(plan)
+    assert need == 8 * (32 + 5 * 49 * 65 + 5 * 3 * 65)
+    fake = ctypes.c_void_p(0x10000)
+    odd = ctypes.c_void_p(0x10004)
+    assert lib.pf_integral_images(None, fake, 64, None, 0, fake, need, None) == 1
+    assert lib.pf_integral_images(plan, fake, 63, None, 0, fake, need, None) == 5
+    assert lib.pf_integral_images(plan, fake, 64, None, 0, fake, need - 1, None) == 7
+    assert lib.pf_integral_images(plan, fake, 64, None, 0, odd, need, None) == 7
+    assert lib.pf_fit_rects(plan, fake, fake, 0, fake, fake, fake, None, None) == 0   # no-op
+    assert lib.pf_fit_rects(plan, fake, fake, -1, fake, fake, fake, None, None) == 2
+    assert lib.pf_fit_rects(plan, None, fake, 3, fake, fake, fake, None, None) == 1
+    assert lib.pf_fit_rects(plan, fake, fake, 3, ctypes.c_void_p(0x10001), fake, fake, None,
+                            None) == 6
+    lib.pf_plan_destroy(plan)

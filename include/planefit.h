@@ -87,14 +87,27 @@ enum { PF_IMPLICIT = 0, PF_EXPLICIT = 1 };
  *                pf_params.kappa_fp64 are solved again in FP64 (status bit 2). */
 enum { PF_PREC_FP64 = 0, PF_PREC_FP32 = 1, PF_PREC_COMPENSATED = 2 };
 
+/* pf_params.flags.
+ *  PF_FLAG_DISPARITY: the input image holds disparity D instead of depth, with
+ *    1/Z = D * disparity_scale (a stereo or structured-light sensor reports
+ *    D = f b / Z, so disparity_scale = 1 / (f b)).  The integrands of Eq. 14
+ *    are then linear in the input: w = D * disparity_scale, no division.
+ *    Validity: D finite and > 0.  Offsets are in the unit of 1/disparity_scale.
+ *    Supported by pf_fit_planes, pf_fit_planes_batch and the backward pass
+ *    (which then returns dL/dD); PF_ERR_UNSUPPORTED for pf_fit_planes_xyz and
+ *    the rectangle fits. */
+enum { PF_FLAG_DISPARITY = 1 };
+
 typedef struct {
   int32_t window;     /* k: odd, 3 <= k <= 63, k <= min(H, W) */
   int32_t mode;       /* PF_IMPLICIT or PF_EXPLICIT */
   int32_t precision;  /* PF_PREC_FP64 or PF_PREC_FP32 */
-  int32_t flags;      /* reserved, must be 0 */
+  int32_t flags;      /* 0 or PF_FLAG_DISPARITY */
   double kappa_flag;  /* implicit mode: set status bit 1 where kappa > this; 0 = never */
   double kappa_fp64;  /* PF_PREC_COMPENSATED, implicit: FP64 re-solve where the FP32
                          kappa exceeds this (0 = 100); ignored otherwise */
+  double disparity_scale;  /* PF_FLAG_DISPARITY: 1/Z = D * disparity_scale (finite, > 0);
+                              ignored otherwise */
 } pf_params;
 
 typedef struct pf_plan pf_plan;
@@ -153,7 +166,8 @@ typedef struct {
 /* Enqueue the fits of n frames (Sec. II-C: many fits from one pass over each
  * frame) in as few launches as possible: up to 32 frames per kernel launch,
  * of any sizes and window sizes, each described by its own plan.  All plans
- * must share mode, precision, kappa_flag and kappa_fp64 (else PF_ERR_UNSUPPORTED).  Every
+ * must share mode, precision, kappa_flag, kappa_fp64 and the disparity setting (else
+ * PF_ERR_UNSUPPORTED).  Every
  * frame is checked on the host as in pf_fit_planes before anything is
  * enqueued; n = 0 is a no-op.  No workspace is needed. */
 pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io, int32_t n,

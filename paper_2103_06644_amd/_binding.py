@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "PF_OK", 1: "PF_ERR_NULL", 2: "PF_ERR_SHAPE", 3: "PF_ERR_WIND
                 7: "PF_ERR_WORKSPACE", 8: "PF_ERR_UNSUPPORTED", 9: "PF_ERR_HIP"}
 MODES = {"implicit": 0, "explicit": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1, "compensated": 2}
+FLAG_DISPARITY = 1
 
 # status byte bits written per pixel
 STATUS_INVALID = 1
@@ -62,7 +63,8 @@ class _BackwardIO(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("window", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("kappa_flag", ctypes.c_double), ("kappa_fp64", ctypes.c_double)]
+                ("kappa_flag", ctypes.c_double), ("kappa_fp64", ctypes.c_double),
+                ("disparity_scale", ctypes.c_double)]
 
 
 _lib = None
@@ -147,7 +149,7 @@ class Plan:
 
     def __init__(self, intrinsics, height: int, width: int, window: int,
                  mode: str = "implicit", precision: str = "fp64", kappa_flag: float = 0.0,
-                 flags: int = 0, kappa_fp64: float = 0.0):
+                 flags: int = 0, kappa_fp64: float = 0.0, disparity_scale: float = 0.0):
         lib = load_library()
         fx, fy, cx, cy = (float(v) for v in intrinsics)
         if mode not in MODES:
@@ -156,7 +158,7 @@ class Plan:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         self._intr = _Intrinsics(fx, fy, cx, cy)
         self._params = _Params(int(window), MODES[mode], PRECISIONS[precision], int(flags),
-                               float(kappa_flag), float(kappa_fp64))
+                               float(kappa_flag), float(kappa_fp64), float(disparity_scale))
         h = ctypes.c_void_p()
         _check(lib.pf_plan_create(ctypes.byref(self._intr), int(height), int(width),
                                   ctypes.byref(self._params), ctypes.byref(h)))
@@ -200,13 +202,17 @@ _plan_cache_lock = threading.Lock()
 
 
 def get_plan(intrinsics, height, width, window, mode="implicit", precision="fp64",
-             kappa_flag=0.0) -> Plan:
+             kappa_flag=0.0, disparity_scale=None) -> Plan:
+    """Cached plan; disparity_scale (1/Z = D * scale) selects disparity input."""
+    ds = 0.0 if disparity_scale is None else float(disparity_scale)
     key = (tuple(float(v) for v in intrinsics), int(height), int(width), int(window), mode,
-           precision, float(kappa_flag))
+           precision, float(kappa_flag), ds)
     with _plan_cache_lock:
         p = _plan_cache.get(key)
         if p is None:
-            p = Plan(intrinsics, height, width, window, mode, precision, kappa_flag)
+            p = Plan(intrinsics, height, width, window, mode, precision, kappa_flag,
+                     flags=FLAG_DISPARITY if disparity_scale is not None else 0,
+                     disparity_scale=ds)
             _plan_cache[key] = p
         return p
 
@@ -237,7 +243,8 @@ class _on_device:
 
 
 def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "implicit",
-               precision: str = "fp64", kappa_flag: float = 0.0, out=None, stream=None):
+               precision: str = "fp64", kappa_flag: float = 0.0, out=None, stream=None,
+               disparity_scale=None):
     """Per-pixel plane fits of a depth frame on the GPU.
 
     depth       float32 tensor [H, W] on a HIP device (unit stride along W)
@@ -245,6 +252,7 @@ def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "
     window      odd window size k
     valid_mask  optional uint8/bool tensor [H, W] on the same device (0 = invalid)
     out         optional (normals [3,H,W], offsets [H,W], residuals [H,W], status [H,W])
+    disparity_scale  if given, `depth` holds disparity D with 1/Z = D * disparity_scale
     Returns (normals, offsets, residuals, status), enqueued on the current stream.
     """
     import torch
@@ -253,7 +261,7 @@ def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "
     if depth.stride(1) != 1:
         raise ValueError("depth must have unit stride along W")
     H, W = depth.shape
-    plan = get_plan(intrinsics, H, W, window, mode, precision, kappa_flag)
+    plan = get_plan(intrinsics, H, W, window, mode, precision, kappa_flag, disparity_scale)
     dev = depth.device
     mptr, mpitch = None, 0
     if valid_mask is not None:
@@ -392,7 +400,8 @@ def _mask_arg(torch, valid_mask, depth):
 
 
 def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="implicit",
-                     precision="fp64", kappa_flag=0.0, outs=None, stream=None):
+                     precision="fp64", kappa_flag=0.0, outs=None, stream=None,
+                     disparity_scale=None):
     """Per-pixel plane fits of several frames (any sizes, per-frame window sizes)
     in as few kernel launches as possible (up to 32 frames per launch).
 
@@ -419,7 +428,7 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
         if d.device != dev:
             raise ValueError("all frames must be on one device")
         H, W = d.shape
-        p = get_plan(intr[i], H, W, ks[i], mode, precision, kappa_flag)
+        p = get_plan(intr[i], H, W, ks[i], mode, precision, kappa_flag, disparity_scale)
         plans.append(p)
         mptr, mpitch = _mask_arg(torch, masks[i], d)
         if outs is None:
@@ -442,7 +451,7 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
 
 def fit_planes_backward(depth, intrinsics, window: int, grad_normals=None, grad_offsets=None,
                         grad_residuals=None, valid_mask=None, *, mode: str = "implicit",
-                        out=None, stream=None):
+                        out=None, stream=None, disparity_scale=None):
     """Gradient of a scalar loss with respect to the depth image, given the
     loss's gradients with respect to the outputs of fit_planes (each optional,
     float32 [3,H,W] / [H,W] / [H,W] on depth's device).  Differentiated in FP64
@@ -451,7 +460,7 @@ def fit_planes_backward(depth, intrinsics, window: int, grad_normals=None, grad_
     _check_depth(torch, depth)
     H, W = depth.shape
     dev = depth.device
-    plan = get_plan(intrinsics, H, W, window, mode, "fp64", 0.0)
+    plan = get_plan(intrinsics, H, W, window, mode, "fp64", 0.0, disparity_scale)
     mptr, mpitch = _mask_arg(torch, valid_mask, depth)
     ptrs = []
     for g, shp in ((grad_normals, (3, H, W)), (grad_offsets, (H, W)), (grad_residuals, (H, W))):
@@ -490,7 +499,7 @@ def _grad_arg(torch, g, shp, dev):
 
 def fit_planes_backward_batch(depths, intrinsics, windows, grad_normals=None, grad_offsets=None,
                               grad_residuals=None, valid_masks=None, *, mode="implicit",
-                              outs=None, stream=None):
+                              outs=None, stream=None, disparity_scale=None):
     """The backward pass of several frames (any sizes, per-frame k) in two
     launches per 32 frames.  Per-frame lists of output gradients (entries or
     whole lists may be None); returns the list of dL/dZ tensors."""
@@ -512,7 +521,7 @@ def fit_planes_backward_batch(depths, intrinsics, windows, grad_normals=None, gr
         if d.device != dev:
             raise ValueError("all frames must be on one device")
         H, W = d.shape
-        p = get_plan(intr[i], H, W, ks[i], mode, "fp64", 0.0)
+        p = get_plan(intr[i], H, W, ks[i], mode, "fp64", 0.0, disparity_scale)
         plans.append(p)
         ws += p.backward_workspace_bytes
         mptr, mpitch = _mask_arg(torch, lists[3][i], d)

@@ -102,6 +102,7 @@ struct FitArgs {
   double kappa_fp64;  // compensated path: FP64 re-solve above this FP32 kappa
   int vec_store;  // outputs 16-byte aligned, W and tile_w multiples of 4
   double* gws;    // backward: per-window moment gradients [4][H][W]
+  double dscale;  // > 0: the input is disparity D with w = D * dscale; 0: depth Z, w = 1/Z
 };
 
 // One frame of a launch, passed by value in the kernel arguments.
@@ -128,6 +129,7 @@ struct LaunchArgs {
   int32_t n_wg;
   double kappa_flag;
   double kappa_fp64;
+  double dscale;  // disparity input scale (0: depth input), shared by the launch's jobs
   double* gws;  // backward pass only (single job): moment-gradient workspace
   Job jobs[kMaxJobs];
 };
@@ -273,11 +275,23 @@ __device__ inline df32 recip(float zf, df32) {
   return fast_two_sum(r, r * e);
 }
 
+// Disparity w of a valid sample: 1/Z for depth input, D * dscale for disparity
+// input (one rounding either way: the product is exact to the last bit of T).
+__device__ inline double disparity(float z, double dscale, double) {
+  return dscale > 0.0 ? double(z) * dscale : recip(z, 0.0);
+}
+__device__ inline float disparity(float z, double dscale, float) {
+  return dscale > 0.0 ? z * float(dscale) : recip(z, 0.0f);
+}
+__device__ inline df32 disparity(float z, double dscale, df32) {
+  return dscale > 0.0 ? df32(z) * to_df32(dscale) : recip(z, df32(0.0f));
+}
+
 template <typename T>
-__device__ inline void add_sample(float z, int y, T w_ref, int y_ref, Cursor<T>& c) {
+__device__ inline void add_sample(float z, int y, T w_ref, int y_ref, Cursor<T>& c, double dscale) {
   // branch-free: invalid samples contribute exact zeros
   const bool ok = depth_valid(z);
-  const T wh = ok ? recip(z, T(0.0f)) - w_ref : T(0.0f);
+  const T wh = ok ? disparity(z, dscale, T(0.0f)) - w_ref : T(0.0f);
   c.w += wh;
   c.yw += T(y - y_ref) * wh;
   c.ww += wh * wh;
@@ -287,9 +301,9 @@ __device__ inline void add_sample(float z, int y, T w_ref, int y_ref, Cursor<T>&
 // The same sample taken out again: recomputed with the same operations, so
 // it is the exact value that was added.
 template <typename T>
-__device__ inline void sub_sample(float z, int y, T w_ref, int y_ref, Cursor<T>& c) {
+__device__ inline void sub_sample(float z, int y, T w_ref, int y_ref, Cursor<T>& c, double dscale) {
   const bool ok = depth_valid(z);
-  const T wh = ok ? recip(z, T(0.0f)) - w_ref : T(0.0f);
+  const T wh = ok ? disparity(z, dscale, T(0.0f)) - w_ref : T(0.0f);
   c.w = c.w - wh;
   c.yw = c.yw - T(y - y_ref) * wh;
   c.ww = c.ww - wh * wh;
@@ -776,6 +790,7 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD>)) void fit_planes
   a.vec_store = job.vec_store;
   a.gws = nullptr;
   if constexpr (BWD) a.gws = la.gws + bwd_ws_offset(la, jb);
+  a.dscale = la.dscale;
 
   __shared__ T sw[TL::rows * kPitch];
   __shared__ T syw[TL::rows * kPitch];
@@ -799,7 +814,7 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD>)) void fit_planes
   {
     const float z = col_used ? load_depth<MASK>(a, x, min(y_ref, a.H - 1)) : 0.0f;
     if (depth_valid(z)) {
-      ws = recip(z, 0.0);
+      ws = disparity(z, a.dscale, 0.0);
       wc = 1.0;
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -838,7 +853,7 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD>)) void fit_planes
       z[j] = (c + j < a.k - 1 && col_used) ? load_depth<MASK>(a, x, yb - a.r + c + j) : 0.0f;
 #pragma unroll
     for (int j = 0; j < TL::rows; ++j)
-      if (c + j < a.k - 1) add_sample<T>(z[j], yb - a.r + c + j, w_ref, y_ref, col);
+      if (c + j < a.k - 1) add_sample<T>(z[j], yb - a.r + c + j, w_ref, y_ref, col, a.dscale);
   }
 
   // depth samples of the current round, loaded one round ahead
@@ -864,8 +879,8 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD>)) void fit_planes
     for (int j = 0; j < TL::rows; ++j) {
       if (j < nr) {
         const int y0 = yg + j;
-        if (y0 > yb) sub_sample<T>(zg[j], y0 - a.r - 1, w_ref, y_ref, col);
-        add_sample<T>(zl[j], y0 + a.r, w_ref, y_ref, col);
+        if (y0 > yb) sub_sample<T>(zg[j], y0 - a.r - 1, w_ref, y_ref, col, a.dscale);
+        add_sample<T>(zl[j], y0 + a.r, w_ref, y_ref, col, a.dscale);
         sw[j * kPitch + li] = col.w;
         syw[j * kPitch + li] = col.yw;
         sww[j * kPitch + li] = col.ww;
@@ -1169,8 +1184,10 @@ __global__ __launch_bounds__(kBlock) void grad_depth_fused(LaunchArgs la) {
           if (MASK && job.mask && job.mask[int64_t(y0) * job.mask_pitch + xi] == 0) z = 0.0f;
           double dz = 0.0;
           if (depth_valid(z)) {
-            const double w = 1.0 / double(z);
-            dz = -(A - Bx - By + 2.0 * w * E) * w * w;
+            // dL/dw, then chained to the input: dw/dZ = -w^2, or dw/dD = dscale
+            const double w = la.dscale > 0.0 ? double(z) * la.dscale : 1.0 / double(z);
+            const double gw = A - Bx - By + 2.0 * w * E;
+            dz = la.dscale > 0.0 ? gw * la.dscale : -gw * w * w;
           }
           job.normals[int64_t(y0) * W + xi] = float(dz);
         }
@@ -1622,6 +1639,9 @@ struct pf_plan {
   pf_intrinsics intr;
   int64_t H, W;
   pf_params params;
+  double dscale() const {
+    return (params.flags & PF_FLAG_DISPARITY) ? params.disparity_scale : 0.0;
+  }
   int k, r;
   double S2, N;
   int tile_w, tile_h, n_strips, n_bands;
@@ -1662,7 +1682,10 @@ pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t widt
   if ((params->mode != PF_IMPLICIT && params->mode != PF_EXPLICIT) ||
       (params->precision != PF_PREC_FP64 && params->precision != PF_PREC_FP32 &&
        params->precision != PF_PREC_COMPENSATED) ||
-      params->flags != 0 || !(params->kappa_flag >= 0.0) || !std::isfinite(params->kappa_flag) ||
+      (params->flags & ~PF_FLAG_DISPARITY) != 0 ||
+      ((params->flags & PF_FLAG_DISPARITY) &&
+       !(params->disparity_scale > 0.0 && std::isfinite(params->disparity_scale))) ||
+      !(params->kappa_flag >= 0.0) || !std::isfinite(params->kappa_flag) ||
       !(params->kappa_fp64 >= 0.0) || !std::isfinite(params->kappa_fp64))
     return PF_ERR_UNSUPPORTED;
   pf_plan* p = new (std::nothrow) pf_plan;
@@ -1742,7 +1765,8 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
     if (p->params.mode != plans[0]->params.mode ||
         p->params.precision != plans[0]->params.precision ||
         p->params.kappa_flag != plans[0]->params.kappa_flag ||
-        p->params.kappa_fp64 != plans[0]->params.kappa_fp64)
+        p->params.kappa_fp64 != plans[0]->params.kappa_fp64 ||
+        p->dscale() != plans[0]->dscale())
       return PF_ERR_UNSUPPORTED;
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -1754,6 +1778,7 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
     std::memset(&la, 0, sizeof(la));
     la.n_jobs = cnt;
     la.kappa_flag = plans[first]->params.kappa_flag;
+    la.dscale = plans[first]->dscale();
     la.kappa_fp64 = plans[first]->params.kappa_fp64 > 0.0 ? plans[first]->params.kappa_fp64
                                                            : kDefaultKappaFp64;
     bool has_mask = false;
@@ -1854,7 +1879,8 @@ pf_status pf_fit_planes_backward_batch(const pf_plan* const* plans, const pf_bac
         (f.grad_offsets && misaligned(f.grad_offsets, 3)) ||
         (f.grad_residuals && misaligned(f.grad_residuals, 3)))
       return PF_ERR_ALIGNMENT;
-    if (p->params.mode != plans[0]->params.mode) return PF_ERR_UNSUPPORTED;
+    if (p->params.mode != plans[0]->params.mode || p->dscale() != plans[0]->dscale())
+      return PF_ERR_UNSUPPORTED;
     need += pf_backward_workspace_bytes(p);
   }
   if (!workspace || workspace_bytes < need || misaligned(workspace, 7)) return PF_ERR_WORKSPACE;
@@ -1868,6 +1894,7 @@ pf_status pf_fit_planes_backward_batch(const pf_plan* const* plans, const pf_bac
     la.n_jobs = cnt;
     la.kappa_flag = 0.0;
     la.kappa_fp64 = kDefaultKappaFp64;
+    la.dscale = plans[0]->dscale();
     la.gws = ws;
     bool has_mask = false;
     int32_t wg = 0;
@@ -1941,7 +1968,7 @@ pf_status pf_fit_planes_xyz(const pf_plan* plan, const float* depth, int64_t dep
                             const uint8_t* mask, int64_t mask_pitch, float* normals,
                             float* offsets, float* residuals, uint8_t* status, void* stream) {
   if (!plan || !depth || !normals || !offsets || !residuals) return PF_ERR_NULL;
-  if (plan->params.precision != PF_PREC_FP64) return PF_ERR_UNSUPPORTED;
+  if (plan->params.precision != PF_PREC_FP64 || plan->dscale() > 0.0) return PF_ERR_UNSUPPORTED;
   if (depth_pitch < plan->W || depth_pitch > INT32_MAX ||
       (mask && (mask_pitch < plan->W || mask_pitch > INT32_MAX)))
     return PF_ERR_PITCH;
@@ -2002,6 +2029,7 @@ pf_status pf_integral_images(const pf_plan* plan, const float* depth, int64_t de
                              const uint8_t* mask, int64_t mask_pitch, void* workspace,
                              size_t workspace_bytes, void* stream) {
   if (!plan || !depth) return PF_ERR_NULL;
+  if (plan->dscale() > 0.0) return PF_ERR_UNSUPPORTED;
   if (depth_pitch < plan->W || (mask && mask_pitch < plan->W)) return PF_ERR_PITCH;
   if ((reinterpret_cast<uintptr_t>(depth) & 3) != 0) return PF_ERR_ALIGNMENT;
   if (!workspace || workspace_bytes < pf_integral_workspace_bytes(plan) ||

@@ -45,7 +45,7 @@ def _create(intr=(525.0, 525.0, 319.5, 239.5), H=480, W=640, k=5, mode=0, prec=0
     (dict(H=0), 2), (dict(W=-3), 2), (dict(H=70000), 2),
     (dict(intr=(0.0, 525.0, 1.0, 1.0)), 4), (dict(intr=(525.0, float("nan"), 1.0, 1.0)), 4),
     (dict(intr=(525.0, 525.0, float("inf"), 1.0)), 4),
-    (dict(mode=2), 8), (dict(prec=7), 8), (dict(flags=1), 8), (dict(kappa=-1.0), 8),
+    (dict(mode=2), 8), (dict(prec=7), 8), (dict(flags=2), 8), (dict(flags=1), 8), (dict(kappa=-1.0), 8),
     (dict(prec=2), 0),
     (dict(), 0), (dict(H=63, W=63, k=63), 0), (dict(mode=1, prec=1, kappa=1e6), 0),
 ])
@@ -233,3 +233,18 @@ def test_rect_argument_checks_return_before_launch():
     assert lib.pf_fit_rects(plan, fake, fake, 3, ctypes.c_void_p(0x10001), fake, fake, None,
                             None) == 6
     lib.pf_plan_destroy(plan)
+
+
+def test_disparity_flag_validation():
+    lib = pf.load_library()
+    for scale, code in ((1.0 / 40.0, 0), (0.0, 8), (-1.0, 8), (float("inf"), 8), (float("nan"), 8)):
+        h = ctypes.c_void_p()
+        got = lib.pf_plan_create(ctypes.byref(_Intrinsics(525.0, 525.0, 319.5, 239.5)), 48, 64,
+                                 ctypes.byref(_Params(5, 0, 0, 1, 0.0, 0.0, scale)), ctypes.byref(h))
+        assert got == code, (scale, got)
+        if h.value:
+            fake = ctypes.c_void_p(0x10000)
+            # the XYZ and rectangle paths take depth only
+            assert lib.pf_fit_planes_xyz(h, fake, 64, None, 0, fake, fake, fake, None, None) == 8
+            assert lib.pf_integral_images(h, fake, 64, None, 0, fake, 1 << 30, None) == 8
+            lib.pf_plan_destroy(h)

@@ -19,10 +19,11 @@ IMPLICIT_SCATTER = 2
 EXPLICIT_NORMALEQ = 3
 XYZ_IMPLICIT = 4
 XYZ_EXPLICIT = 5
+IMPLICIT_LITERAL = 6
 
 _MODES = {"implicit": IMPLICIT, "explicit": EXPLICIT, "implicit_scatter": IMPLICIT_SCATTER,
           "explicit_normaleq": EXPLICIT_NORMALEQ, "xyz_implicit": XYZ_IMPLICIT,
-          "xyz_explicit": XYZ_EXPLICIT}
+          "xyz_explicit": XYZ_EXPLICIT, "implicit_literal": IMPLICIT_LITERAL}
 
 _lib = None
 _dp = ctypes.POINTER(ctypes.c_double)

@@ -68,6 +68,59 @@ void pfo_jacobi3(const double a_in[9], double evals[3], double evecs[9]) {
   }
 }
 
+/* 4x4 symmetric eigen-decomposition by the same cyclic Jacobi method, applying
+ * each rotation to rows and columns p, q directly; eigenvalues ascending,
+ * eigenvectors in the columns of evecs (row-major 4x4). */
+static void jacobi4(const double a_in[16], double evals[4], double evecs[16]) {
+  double A[4][4], V[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      A[i][j] = 0.5 * (a_in[4 * i + j] + a_in[4 * j + i]);
+      V[i][j] = i == j ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      dia += A[i][i] * A[i][i];
+      for (int j = i + 1; j < 4; ++j) off += A[i][j] * A[i][j];
+    }
+    if (off == 0.0 || off <= 1e-36 * dia) break;
+    for (int p = 0; p < 3; ++p)
+      for (int q = p + 1; q < 4; ++q) {
+        if (A[p][q] == 0.0) continue;
+        double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + hypot(1.0, tau));
+        double c = 1.0 / hypot(1.0, t), sn = t * c;
+        for (int k = 0; k < 4; ++k) { /* columns p, q: A <- A J */
+          double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 4; ++k) { /* rows p, q: A <- J^T A */
+          double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+        A[p][q] = A[q][p] = 0.0;
+        for (int k = 0; k < 4; ++k) {
+          double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - sn * vkq;
+          V[k][q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  int order[4] = {0, 1, 2, 3};
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (A[order[j]][order[j]] < A[order[i]][order[i]]) {
+        int t = order[i]; order[i] = order[j]; order[j] = t;
+      }
+  for (int i = 0; i < 4; ++i) {
+    evals[i] = A[order[i]][order[i]];
+    for (int r = 0; r < 4; ++r) evecs[4 * r + i] = V[r][order[i]];
+  }
+}
+
 /* ---------------------------------------------------------------------------
  * Window gathering and back-projection (Eq. 1, delta = 0).
  * ------------------------------------------------------------------------- */
@@ -184,6 +237,28 @@ static void fit_implicit_scatter(const double* X, const double* Y, const double*
   unit_from(n, f->n);
   f->d = -(S[0][3] * f->n[0] + S[1][3] * f->n[1] + S[2][3] * f->n[2]) / S[3][3];
   f->kappa = (ev[1] > ev[0]) ? ev[2] / (ev[1] - ev[0]) : INFINITY;
+}
+
+/* The implicit fit with the constraint exactly as Sec. II-A states it,
+ * |(a, b, c, d)| = 1: the eigenvector of the smallest eigenvalue of the 4x4
+ * scatter of [u, v, 1, w] (Eq. 14), then scaled to a unit normal.  Unlike the
+ * |(a, b, c)| = 1 fit it depends on the depth unit (d multiplies 1/Z). */
+static void fit_implicit_literal(const double* X, const double* Y, const double* Z, int N,
+                                 fit_t* f) {
+  double S[16] = {0};
+  for (int i = 0; i < N; ++i) {
+    double m[4] = {X[i] / Z[i], Y[i] / Z[i], 1.0, 1.0 / Z[i]};
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) S[4 * a + b] += m[a] * m[b];
+  }
+  double ev[4], V[16];
+  jacobi4(S, ev, V);
+  double s = sqrt(V[0] * V[0] + V[4] * V[4] + V[8] * V[8]);
+  f->n[0] = V[0] / s;
+  f->n[1] = V[4] / s;
+  f->n[2] = V[8] / s;
+  f->d = V[12] / s;
+  f->kappa = (ev[1] > ev[0]) ? ev[3] / (ev[1] - ev[0]) : INFINITY;
 }
 
 /* Explicit plane from coefficients alpha of a u + b v + c = 1/Z: multiplying by Z
@@ -313,6 +388,7 @@ static void fit_gathered(const double* X, const double* Y, const double* Z, int 
     case PFO_EXPLICIT: fit_explicit_centred(X, Y, Z, N, &f); break;
     case PFO_EXPLICIT_NORMALEQ: fit_explicit_normaleq(X, Y, Z, N, &f); break;
     case PFO_XYZ_IMPLICIT: fit_implicit_pca(X, Y, Z, N, 0, &f); break;
+    case PFO_IMPLICIT_LITERAL: fit_implicit_literal(X, Y, Z, N, &f); break;
     default: fit_xyz_explicit(X, Y, Z, N, &f); break;
   }
   orient(&f);
@@ -327,7 +403,7 @@ static void fit_gathered(const double* X, const double* Y, const double* Z, int 
 }
 
 static int bad_args(int64_t H, int64_t W, int k, int mode) {
-  return H <= 0 || W <= 0 || k < 1 || k > KMAX || (k % 2) == 0 || mode < 0 || mode > 5;
+  return H <= 0 || W <= 0 || k < 1 || k > KMAX || (k % 2) == 0 || mode < 0 || mode > 6;
 }
 
 int pfo_fit_planes(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
@@ -386,7 +462,7 @@ int pfo_fit_rects(const double* depth, int64_t H, int64_t W, const uint8_t* mask
                   int32_t mode, int32_t threads, double* normals, double* offsets,
                   double* residuals, double* kappa, uint8_t* status) {
   if (!depth || !rects || !normals || !offsets || !residuals || count < 0 || H <= 0 ||
-      W <= 0 || mode < 0 || mode > 5)
+      W <= 0 || mode < 0 || mode > 6)
     return -1;
   cam_t cam = {fx, fy, cx, cy};
 #ifdef _OPENMP

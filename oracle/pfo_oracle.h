@@ -23,6 +23,10 @@
  *    of 1/Z on (tan(theta_x), tan(theta_y), 1), solved on centred regressors.
  *  - PFO_EXPLICIT_NORMALEQ: Eq. 15 solved literally as (M^T M)^-1 M^T b
  *    (Eq. 16) by Gaussian elimination; cross-check of PFO_EXPLICIT.
+ *  - PFO_IMPLICIT_LITERAL: the implicit RGBD fit with the constraint as
+ *    Sec. II-A states it, |(a, b, c, d)| = 1: smallest eigenvector of the 4x4
+ *    scatter of Eq. 14 (Jacobi), scaled to a unit normal; kappa is
+ *    l4 / (l2 - l1) of that 4x4.  Depends on the depth unit.
  *  - PFO_XYZ_IMPLICIT / PFO_XYZ_EXPLICIT: the standard fits of Eq. 3 and
  *    Eq. 7 on the back-projected points (unweighted); cross-checks only.
  *
@@ -52,7 +56,8 @@ enum {
   PFO_IMPLICIT_SCATTER = 2,
   PFO_EXPLICIT_NORMALEQ = 3,
   PFO_XYZ_IMPLICIT = 4,
-  PFO_XYZ_EXPLICIT = 5
+  PFO_XYZ_EXPLICIT = 5,
+  PFO_IMPLICIT_LITERAL = 6
 };
 
 /* Returns 0 on success, -1 on a bad argument. threads <= 0 means all cores. */

@@ -72,7 +72,14 @@ typedef struct {
   double fx, fy, cx, cy;
 } pf_intrinsics;
 
-enum { PF_IMPLICIT = 0, PF_EXPLICIT = 1 };
+/* PF_IMPLICIT_LITERAL: the implicit fit with the constraint exactly as Sec. II-A
+ * states it, |(a, b, c, d)| = 1 (smallest eigenvector of the 4x4 scatter of
+ * Eq. 14), scaled to a unit normal afterwards.  It mixes units (d multiplies
+ * 1/Z), so its result depends on the depth unit; PF_IMPLICIT constrains
+ * |(a, b, c)| = 1 instead.  For comparison: FP64 only, kappa_flag must be 0,
+ * and only pf_fit_planes / pf_fit_planes_batch accept it (PF_ERR_UNSUPPORTED
+ * elsewhere). */
+enum { PF_IMPLICIT = 0, PF_EXPLICIT = 1, PF_IMPLICIT_LITERAL = 2 };
 
 /* Arithmetic of the window moments and the per-pixel solve.
  *  PF_PREC_FP64: disparity integrands, integral-image sums and the solve in

@@ -19,7 +19,7 @@ PF_OK = 0
 STATUS_NAMES = {0: "PF_OK", 1: "PF_ERR_NULL", 2: "PF_ERR_SHAPE", 3: "PF_ERR_WINDOW",
                 4: "PF_ERR_INTRINSICS", 5: "PF_ERR_PITCH", 6: "PF_ERR_ALIGNMENT",
                 7: "PF_ERR_WORKSPACE", 8: "PF_ERR_UNSUPPORTED", 9: "PF_ERR_HIP"}
-MODES = {"implicit": 0, "explicit": 1}
+MODES = {"implicit": 0, "explicit": 1, "implicit_literal": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "compensated": 2}
 FLAG_DISPARITY = 1
 

@@ -67,6 +67,8 @@ template <>
 struct Tiling<PF_IMPLICIT> {
   static constexpr int rows = 4, run = 4, sub = 72;
 };
+template <>
+struct Tiling<PF_IMPLICIT_LITERAL> : Tiling<PF_IMPLICIT> {};
 constexpr int kPitch = 288;  // LDS entries per row, >= kBlock for both tilings
 static_assert(Tiling<PF_EXPLICIT>::run * Tiling<PF_EXPLICIT>::sub == kPitch, "pitch");
 static_assert(Tiling<PF_IMPLICIT>::run * Tiling<PF_IMPLICIT>::sub == kPitch, "pitch");
@@ -529,6 +531,113 @@ __device__ inline void finish_implicit(const FitArgs& a, const Implicit3<S>& c, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// The implicit fit with the constraint exactly as Sec. II-A states it,
+// |(a, b, c, d)| = 1: the eigenvector of the smallest eigenvalue of the 4x4
+// scatter of the monomials [u, v, 1, w] (Eq. 14), assembled here from the
+// window's centred moments and the closed-form camera block.  FP64.
+//   f(l) = det(S - l I) = (l1 - l)(l2 - l)(l3 - l)(l4 - l) is positive,
+//   decreasing and convex on (-inf, l1], and c0/c1 = 1/sum(1/li) <= l1, so
+//   Halley's iteration from c0/c1 climbs to l1 as for the 3x3.  The eigenvector
+//   is the best-conditioned generalised cross product of three rows of S - l1 I
+//   (the cofactors of a 3x4 block).
+// ---------------------------------------------------------------------------
+__device__ inline double det3g(const double* r0, const double* r1, const double* r2, int skip) {
+  int c[3], n = 0;
+  for (int j = 0; j < 4; ++j)
+    if (j != skip) c[n++] = j;
+  return r0[c[0]] * (r1[c[1]] * r2[c[2]] - r1[c[2]] * r2[c[1]]) -
+         r0[c[1]] * (r1[c[0]] * r2[c[2]] - r1[c[2]] * r2[c[0]]) +
+         r0[c[2]] * (r1[c[0]] * r2[c[1]] - r1[c[1]] * r2[c[0]]);
+}
+
+__device__ inline PixelOut solve_literal(const FitArgs& a, const Moments<double>& m, double uc,
+                                         double vc) {
+  PixelOut o;
+  o.st = 0;
+  o.kappa = 0.0f;
+  const double N = a.N, S2 = a.S2, ifx = a.inv_fx, ify = a.inv_fy;
+  double S[4][4];
+  S[0][0] = N * uc * uc + S2 * ifx * ifx;
+  S[0][1] = N * uc * vc;
+  S[0][2] = N * uc;
+  S[0][3] = uc * m.Sw + m.Sxw * ifx;
+  S[1][1] = N * vc * vc + S2 * ify * ify;
+  S[1][2] = N * vc;
+  S[1][3] = vc * m.Sw + m.Syw * ify;
+  S[2][2] = N;
+  S[2][3] = m.Sw;
+  S[3][3] = m.Sww;
+  const double sc = fmax(fmax(S[0][0], S[1][1]), fmax(S[2][2], S[3][3]));
+  const double is = ldexp(1.0, -ilogb(sc));
+  double B[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = i; j < 4; ++j) B[i][j] = B[j][i] = S[i][j] * is;
+  // characteristic polynomial l^4 - c3 l^3 + c2 l^2 - c1 l + c0
+  const double c3 = B[0][0] + B[1][1] + B[2][2] + B[3][3];
+  double c2 = 0.0;
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j) c2 += B[i][i] * B[j][j] - B[i][j] * B[i][j];
+  double c1 = 0.0;
+  for (int r = 0; r < 4; ++r) {  // principal 3x3 minors: drop row and column r
+    const int i = r == 0 ? 1 : 0, j = r <= 1 ? 2 : 1, k = r <= 2 ? 3 : 2;
+    c1 += det3(B[i][i], B[i][j], B[i][k], B[j][j], B[j][k], B[k][k]);
+  }
+  const double c0 = B[0][0] * det3g(B[1], B[2], B[3], 0) - B[0][1] * det3g(B[1], B[2], B[3], 1) +
+                    B[0][2] * det3g(B[1], B[2], B[3], 2) - B[0][3] * det3g(B[1], B[2], B[3], 3);
+  double l = 0.0;
+  if (c0 > 0.0 && c1 > 0.0) {
+    l = c0 * rcp_nr(c1);
+    for (int it = 0; it < 32; ++it) {
+      const double f = (((l - c3) * l + c2) * l - c1) * l + c0;
+      const double fp = ((4.0 * l - 3.0 * c3) * l + 2.0 * c2) * l - c1;
+      const double fpp = (12.0 * l - 6.0 * c3) * l + 2.0 * c2;
+      if (!(f > 0.0) || !(fp < 0.0)) break;
+      const double den = 2.0 * fp * fp - f * fpp;
+      if (!(den > 0.0)) break;
+      const double ln = l - 2.0 * f * fp * rcp_raw(den);
+      if (!(ln > l)) break;
+      const double step = ln - l;
+      l = ln;
+      if (step <= 1e-14) break;
+    }
+  }
+  double A[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) A[i][j] = B[i][j] - (i == j ? l : 0.0);
+  double v[4] = {0.0, 0.0, 0.0, 1.0}, best = 0.0;
+  for (int r = 0; r < 4; ++r) {  // drop row r, cofactors of the remaining 3x4 block
+    const double* q0 = A[r == 0 ? 1 : 0];
+    const double* q1 = A[r <= 1 ? 2 : 1];
+    const double* q2 = A[r <= 2 ? 3 : 2];
+    double t[4];
+    double nn = 0.0;
+    for (int j = 0; j < 4; ++j) {
+      t[j] = ((j & 1) ? -1.0 : 1.0) * det3g(q0, q1, q2, j);
+      nn += t[j] * t[j];
+    }
+    if (nn > best) {
+      best = nn;
+      for (int j = 0; j < 4; ++j) v[j] = t[j];
+    }
+  }
+  const double sn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  double n0 = v[0] / sn, n1 = v[1] / sn, n2 = v[2] / sn, d = v[3] / sn;
+  if (d < 0.0) {
+    d = -d; n0 = -n0; n1 = -n1; n2 = -n2;
+  }
+  // residual: S a = l1 a for the unit 4-vector a = v/|v|, so the sum of squares
+  // of n.(u, v, 1) + d w is l1 |v|^2 / sn^2
+  const double vn2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3];
+  const double l1 = ldexp(fmax(l, 0.0), ilogb(sc));
+  o.n0 = float(n0);
+  o.n1 = float(n1);
+  o.n2 = float(n2);
+  o.d = float(d);
+  o.res = float(sqrt(l1 * vn2 / (sn * sn) * a.inv_N));
+  return o;
+}
+
 template <typename S, int MODE>
 __device__ inline PixelOut solve_moments(const FitArgs& a, const Moments<S>& m, int x0, int y0) {
   PixelOut o;
@@ -537,7 +646,9 @@ __device__ inline PixelOut solve_moments(const FitArgs& a, const Moments<S>& m, 
   const S iN = S(a.inv_N), S2 = S(a.S2), iS2 = S(a.inv_S2);
   const S uc = (S(x0) - S(a.cx)) * S(a.inv_fx);
   const S vc = (S(y0) - S(a.cy)) * S(a.inv_fy);
-  if (MODE == PF_EXPLICIT) {
+  if constexpr (MODE == PF_IMPLICIT_LITERAL) {
+    return solve_literal(a, m, uc, vc);
+  } else if (MODE == PF_EXPLICIT) {
     // Eq. 15 in centred regressors (x', y', 1): a' = Sxw/S2, b' = Syw/S2, c' = Sw/N;
     // with the cancellation-prone differences already formed, single precision suffices.
     const float ap = float(m.Sxw * iS2), bp = float(m.Syw * iS2), cp = float(m.Sw * iN);
@@ -993,7 +1104,7 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD>)) void fit_planes
           a.gws[2 * a.plane + pp] = mg.Sy;
           a.gws[3 * a.plane + pp] = mg.Sww;
         }
-      } else if (MODE == PF_IMPLICIT) {
+      } else if (MODE != PF_EXPLICIT) {
         // the eigen-solve is large: keep the loop rolled and store each pixel directly
         const int64_t prow = (int64_t)y0 * a.W + ox0;
 #pragma unroll 1
@@ -1679,7 +1790,10 @@ pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t widt
     return PF_ERR_INTRINSICS;
   const int k = params->window;
   if (k < 3 || k > kMaxWindow || (k % 2) == 0 || k > height || k > width) return PF_ERR_WINDOW;
-  if ((params->mode != PF_IMPLICIT && params->mode != PF_EXPLICIT) ||
+  if ((params->mode != PF_IMPLICIT && params->mode != PF_EXPLICIT &&
+       params->mode != PF_IMPLICIT_LITERAL) ||
+      (params->mode == PF_IMPLICIT_LITERAL &&
+       (params->precision != PF_PREC_FP64 || params->kappa_flag != 0.0)) ||
       (params->precision != PF_PREC_FP64 && params->precision != PF_PREC_FP32 &&
        params->precision != PF_PREC_COMPENSATED) ||
       (params->flags & ~PF_FLAG_DISPARITY) != 0 ||
@@ -1825,7 +1939,10 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
       if (has_mask) PF_LAUNCH(T, PF_IMPLICIT, true); else PF_LAUNCH(T, PF_IMPLICIT, false); \
     }                                                                          \
   } while (0)
-    if (prec == PF_PREC_FP64)
+    if (prec == PF_PREC_FP64 && plans[first]->params.mode == PF_IMPLICIT_LITERAL) {
+      if (has_mask) PF_LAUNCH(double, PF_IMPLICIT_LITERAL, true);
+      else PF_LAUNCH(double, PF_IMPLICIT_LITERAL, false);
+    } else if (prec == PF_PREC_FP64)
       PF_LAUNCH_MODES(double);
     else if (prec == PF_PREC_FP32)
       PF_LAUNCH_MODES(float);
@@ -1879,7 +1996,8 @@ pf_status pf_fit_planes_backward_batch(const pf_plan* const* plans, const pf_bac
         (f.grad_offsets && misaligned(f.grad_offsets, 3)) ||
         (f.grad_residuals && misaligned(f.grad_residuals, 3)))
       return PF_ERR_ALIGNMENT;
-    if (p->params.mode != plans[0]->params.mode || p->dscale() != plans[0]->dscale())
+    if (p->params.mode != plans[0]->params.mode || p->dscale() != plans[0]->dscale() ||
+        p->params.mode == PF_IMPLICIT_LITERAL)
       return PF_ERR_UNSUPPORTED;
     need += pf_backward_workspace_bytes(p);
   }
@@ -1968,7 +2086,9 @@ pf_status pf_fit_planes_xyz(const pf_plan* plan, const float* depth, int64_t dep
                             const uint8_t* mask, int64_t mask_pitch, float* normals,
                             float* offsets, float* residuals, uint8_t* status, void* stream) {
   if (!plan || !depth || !normals || !offsets || !residuals) return PF_ERR_NULL;
-  if (plan->params.precision != PF_PREC_FP64 || plan->dscale() > 0.0) return PF_ERR_UNSUPPORTED;
+  if (plan->params.precision != PF_PREC_FP64 || plan->dscale() > 0.0 ||
+      plan->params.mode == PF_IMPLICIT_LITERAL)
+    return PF_ERR_UNSUPPORTED;
   if (depth_pitch < plan->W || depth_pitch > INT32_MAX ||
       (mask && (mask_pitch < plan->W || mask_pitch > INT32_MAX)))
     return PF_ERR_PITCH;
@@ -2029,7 +2149,7 @@ pf_status pf_integral_images(const pf_plan* plan, const float* depth, int64_t de
                              const uint8_t* mask, int64_t mask_pitch, void* workspace,
                              size_t workspace_bytes, void* stream) {
   if (!plan || !depth) return PF_ERR_NULL;
-  if (plan->dscale() > 0.0) return PF_ERR_UNSUPPORTED;
+  if (plan->dscale() > 0.0 || plan->params.mode == PF_IMPLICIT_LITERAL) return PF_ERR_UNSUPPORTED;
   if (depth_pitch < plan->W || (mask && mask_pitch < plan->W)) return PF_ERR_PITCH;
   if ((reinterpret_cast<uintptr_t>(depth) & 3) != 0) return PF_ERR_ALIGNMENT;
   if (!workspace || workspace_bytes < pf_integral_workspace_bytes(plan) ||
@@ -2065,6 +2185,7 @@ pf_status pf_fit_rects(const pf_plan* plan, const void* workspace, const int32_t
   if (n < 0) return PF_ERR_SHAPE;
   if (n == 0) return PF_OK;
   if (!plan || !workspace || !rects || !normals || !offsets || !residuals) return PF_ERR_NULL;
+  if (plan->params.mode == PF_IMPLICIT_LITERAL) return PF_ERR_UNSUPPORTED;
   if (n > int64_t(INT32_MAX) * kBlock / 4) return PF_ERR_SHAPE;
   auto misaligned = [](const void* q, uintptr_t m) { return (reinterpret_cast<uintptr_t>(q) & m) != 0; };
   if (misaligned(rects, 3) || misaligned(normals, 3) || misaligned(offsets, 3) ||

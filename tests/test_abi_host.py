@@ -45,7 +45,8 @@ def _create(intr=(525.0, 525.0, 319.5, 239.5), H=480, W=640, k=5, mode=0, prec=0
     (dict(H=0), 2), (dict(W=-3), 2), (dict(H=70000), 2),
     (dict(intr=(0.0, 525.0, 1.0, 1.0)), 4), (dict(intr=(525.0, float("nan"), 1.0, 1.0)), 4),
     (dict(intr=(525.0, 525.0, float("inf"), 1.0)), 4),
-    (dict(mode=2), 8), (dict(prec=7), 8), (dict(flags=2), 8), (dict(flags=1), 8), (dict(kappa=-1.0), 8),
+    (dict(mode=3), 8), (dict(mode=2, prec=1), 8), (dict(mode=2, kappa=5.0), 8), (dict(mode=2), 0),
+    (dict(prec=7), 8), (dict(flags=2), 8), (dict(flags=1), 8), (dict(kappa=-1.0), 8),
     (dict(prec=2), 0),
     (dict(), 0), (dict(H=63, W=63, k=63), 0), (dict(mode=1, prec=1, kappa=1e6), 0),
 ])

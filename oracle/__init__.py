@@ -47,6 +47,12 @@ def _load():
     lib.pfo_fit_points.argtypes = [_dp, i64, i64, _u8p, d, d, d, d, i32, i32, _i64p, _i64p,
                                    i64, i32, _dp, _dp, _dp, _dp, _u8p]
     lib.pfo_fit_points.restype = ctypes.c_int
+    lib.pfo_fit_planes_partial.argtypes = [_dp, i64, i64, _u8p, d, d, d, d, i32, i32, i32, i32,
+                                           _dp, _dp, _dp, _dp, _u8p]
+    lib.pfo_fit_planes_partial.restype = ctypes.c_int
+    lib.pfo_fit_points_partial.argtypes = [_dp, i64, i64, _u8p, d, d, d, d, i32, i32, i32,
+                                           _i64p, _i64p, i64, i32, _dp, _dp, _dp, _dp, _u8p]
+    lib.pfo_fit_points_partial.restype = ctypes.c_int
     lib.pfo_fit_rects.argtypes = [_dp, i64, i64, _u8p, d, d, d, d,
                                   ctypes.POINTER(ctypes.c_int32), i64, i32, i32, _dp, _dp, _dp,
                                   _dp, _u8p]
@@ -107,8 +113,9 @@ def _mode(mode):
     return _MODES[mode] if isinstance(mode, str) else int(mode)
 
 
-def fit_planes(depth, intrinsics, k, mode="implicit", mask=None, threads=0):
-    """Per-pixel k x k window fits over the whole frame.
+def fit_planes(depth, intrinsics, k, mode="implicit", mask=None, threads=0, min_valid=None):
+    """Per-pixel k x k window fits over the whole frame (partial windows with at
+    least min_valid valid pixels when min_valid is given).
 
     Returns a dict of FP64 arrays: normals [3,H,W], offsets [H,W], residuals [H,W],
     kappa [H,W] and status uint8 [H,W] (1 = invalid window)."""
@@ -118,16 +125,22 @@ def fit_planes(depth, intrinsics, k, mode="implicit", mask=None, threads=0):
     out = dict(normals=np.empty((3, H, W)), offsets=np.empty((H, W)),
                residuals=np.empty((H, W)), kappa=np.empty((H, W)),
                status=np.empty((H, W), np.uint8))
-    rc = _load().pfo_fit_planes(_ptr(depth), H, W, _ptr(mask, _u8p), fx, fy, cx, cy, int(k),
-                                _mode(mode), int(threads), _ptr(out["normals"]),
-                                _ptr(out["offsets"]), _ptr(out["residuals"]),
-                                _ptr(out["kappa"]), _ptr(out["status"], _u8p))
+    outs = (_ptr(out["normals"]), _ptr(out["offsets"]), _ptr(out["residuals"]),
+            _ptr(out["kappa"]), _ptr(out["status"], _u8p))
+    if min_valid is None:
+        rc = _load().pfo_fit_planes(_ptr(depth), H, W, _ptr(mask, _u8p), fx, fy, cx, cy, int(k),
+                                    _mode(mode), int(threads), *outs)
+    else:
+        rc = _load().pfo_fit_planes_partial(_ptr(depth), H, W, _ptr(mask, _u8p), fx, fy, cx, cy,
+                                            int(k), _mode(mode), int(min_valid), int(threads),
+                                            *outs)
     if rc != 0:
         raise ValueError("oracle: bad arguments")
     return out
 
 
-def fit_points(depth, intrinsics, k, xs, ys, mode="implicit", mask=None, threads=0):
+def fit_points(depth, intrinsics, k, xs, ys, mode="implicit", mask=None, threads=0,
+               min_valid=None):
     """Fits at the window centres (xs[i], ys[i]) only; arrays of length len(xs)."""
     depth, mask = _prep(depth, mask)
     H, W = depth.shape
@@ -137,11 +150,16 @@ def fit_points(depth, intrinsics, k, xs, ys, mode="implicit", mask=None, threads
     fx, fy, cx, cy = map(float, intrinsics)
     out = dict(normals=np.empty((3, n)), offsets=np.empty(n), residuals=np.empty(n),
                kappa=np.empty(n), status=np.empty(n, np.uint8))
-    rc = _load().pfo_fit_points(_ptr(depth), H, W, _ptr(mask, _u8p), fx, fy, cx, cy, int(k),
-                                _mode(mode), _ptr(xs, _i64p), _ptr(ys, _i64p), n, int(threads),
-                                _ptr(out["normals"]), _ptr(out["offsets"]),
-                                _ptr(out["residuals"]), _ptr(out["kappa"]),
-                                _ptr(out["status"], _u8p))
+    outs = (_ptr(out["normals"]), _ptr(out["offsets"]), _ptr(out["residuals"]),
+            _ptr(out["kappa"]), _ptr(out["status"], _u8p))
+    if min_valid is None:
+        rc = _load().pfo_fit_points(_ptr(depth), H, W, _ptr(mask, _u8p), fx, fy, cx, cy, int(k),
+                                    _mode(mode), _ptr(xs, _i64p), _ptr(ys, _i64p), n,
+                                    int(threads), *outs)
+    else:
+        rc = _load().pfo_fit_points_partial(_ptr(depth), H, W, _ptr(mask, _u8p), fx, fy, cx, cy,
+                                            int(k), _mode(mode), int(min_valid), _ptr(xs, _i64p),
+                                            _ptr(ys, _i64p), n, int(threads), *outs)
     if rc != 0:
         raise ValueError("oracle: bad arguments")
     return out

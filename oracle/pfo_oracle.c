@@ -156,10 +156,44 @@ static int gather_rect(const double* depth, int64_t H, int64_t W, const uint8_t*
   return n;
 }
 
-static int gather_window(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
-                         const cam_t* cam, int k, int64_t x0, int64_t y0, double* X,
-                         double* Y, double* Z) {
+/* Partial windows: only the valid pixels of the k x k window (those inside the
+ * image with valid depth) are back-projected; the window is fitted iff there are
+ * at least max(min_valid, 3) of them and they do not all lie on one line of the
+ * pixel grid (else the plane is undetermined); -1 otherwise. */
+static int gather_partial(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
+                          const cam_t* cam, int k, int64_t x0, int64_t y0, int min_valid,
+                          double* X, double* Y, double* Z) {
   const int r = k / 2;
+  int n = 0, have_a = 0, have_b = 0, spread = 0;
+  int64_t ax = 0, ay = 0, bx = 0, by = 0;
+  for (int64_t y = y0 - r; y <= y0 + r; ++y)
+    for (int64_t x = x0 - r; x <= x0 + r; ++x) {
+      if (x < 0 || y < 0 || x >= W || y >= H) continue;
+      int64_t idx = y * W + x;
+      if (!pixel_valid(depth, mask, idx)) continue;
+      if (!have_a) {
+        ax = x; ay = y; have_a = 1;
+      } else if (!have_b) {
+        bx = x; by = y; have_b = 1;
+      } else if ((bx - ax) * (y - ay) - (by - ay) * (x - ax) != 0) {
+        spread = 1; /* three valid pixels not on one line */
+      }
+      double z = depth[idx];
+      X[n] = ((double)x - cam->cx) * z / cam->fx;
+      Y[n] = ((double)y - cam->cy) * z / cam->fy;
+      Z[n] = z;
+      ++n;
+    }
+  const int need = min_valid > 3 ? min_valid : 3;
+  return (n >= need && spread) ? n : -1;
+}
+
+static int gather_window(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
+                         const cam_t* cam, int k, int64_t x0, int64_t y0, int min_valid,
+                         double* X, double* Y, double* Z) {
+  const int r = k / 2;
+  if (min_valid > 0 && min_valid < k * k)
+    return gather_partial(depth, H, W, mask, cam, k, x0, y0, min_valid, X, Y, Z);
   return gather_rect(depth, H, W, mask, cam, x0 - r, y0 - r, k, k, X, Y, Z);
 }
 
@@ -366,11 +400,12 @@ static void fit_gathered(const double* X, const double* Y, const double* Z, int 
                          double* residuals, double* kappa, uint8_t* status);
 
 static void fit_one(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
-                    const cam_t* cam, int k, int mode, int64_t x0, int64_t y0, int64_t o,
+                    const cam_t* cam, int k, int mode, int min_valid, int64_t x0, int64_t y0,
+                    int64_t o,
                     int64_t plane, double* normals, double* offsets, double* residuals,
                     double* kappa, uint8_t* status, double* buf) {
   double *X = buf, *Y = buf + k * k, *Z = buf + 2 * k * k;
-  int N = gather_window(depth, H, W, mask, cam, k, x0, y0, X, Y, Z);
+  int N = gather_window(depth, H, W, mask, cam, k, x0, y0, min_valid, X, Y, Z);
   fit_gathered(X, Y, Z, N, mode, o, plane, normals, offsets, residuals, kappa, status);
 }
 
@@ -406,10 +441,10 @@ static int bad_args(int64_t H, int64_t W, int k, int mode) {
   return H <= 0 || W <= 0 || k < 1 || k > KMAX || (k % 2) == 0 || mode < 0 || mode > 6;
 }
 
-int pfo_fit_planes(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
-                   double fx, double fy, double cx, double cy, int32_t k, int32_t mode,
-                   int32_t threads, double* normals, double* offsets, double* residuals,
-                   double* kappa, uint8_t* status) {
+static int fit_planes_impl(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
+                           double fx, double fy, double cx, double cy, int32_t k, int32_t mode,
+                           int32_t min_valid, int32_t threads, double* normals, double* offsets,
+                           double* residuals, double* kappa, uint8_t* status) {
   if (!depth || !normals || !offsets || !residuals || bad_args(H, W, k, mode)) return -1;
   cam_t cam = {fx, fy, cx, cy};
   int64_t plane = H * W;
@@ -424,18 +459,18 @@ int pfo_fit_planes(const double* depth, int64_t H, int64_t W, const uint8_t* mas
 #endif
     for (int64_t y = 0; y < H; ++y)
       for (int64_t x = 0; x < W; ++x)
-        fit_one(depth, H, W, mask, &cam, k, mode, x, y, y * W + x, plane, normals, offsets,
-                residuals, kappa, status, buf);
+        fit_one(depth, H, W, mask, &cam, k, mode, min_valid, x, y, y * W + x, plane, normals,
+                offsets, residuals, kappa, status, buf);
     free(buf);
   }
   return 0;
 }
 
-int pfo_fit_points(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
-                   double fx, double fy, double cx, double cy, int32_t k, int32_t mode,
-                   const int64_t* xs, const int64_t* ys, int64_t count, int32_t threads,
-                   double* normals, double* offsets, double* residuals, double* kappa,
-                   uint8_t* status) {
+static int fit_points_impl(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
+                           double fx, double fy, double cx, double cy, int32_t k, int32_t mode,
+                           int32_t min_valid, const int64_t* xs, const int64_t* ys,
+                           int64_t count, int32_t threads, double* normals, double* offsets,
+                           double* residuals, double* kappa, uint8_t* status) {
   if (!depth || !xs || !ys || !normals || !offsets || !residuals || count < 0 ||
       bad_args(H, W, k, mode))
     return -1;
@@ -450,11 +485,47 @@ int pfo_fit_points(const double* depth, int64_t H, int64_t W, const uint8_t* mas
 #pragma omp for schedule(dynamic, 64)
 #endif
     for (int64_t i = 0; i < count; ++i)
-      fit_one(depth, H, W, mask, &cam, k, mode, xs[i], ys[i], i, count, normals, offsets,
-              residuals, kappa, status, buf);
+      fit_one(depth, H, W, mask, &cam, k, mode, min_valid, xs[i], ys[i], i, count, normals,
+              offsets, residuals, kappa, status, buf);
     free(buf);
   }
   return 0;
+}
+
+int pfo_fit_planes(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
+                   double fx, double fy, double cx, double cy, int32_t k, int32_t mode,
+                   int32_t threads, double* normals, double* offsets, double* residuals,
+                   double* kappa, uint8_t* status) {
+  return fit_planes_impl(depth, H, W, mask, fx, fy, cx, cy, k, mode, 0, threads, normals,
+                         offsets, residuals, kappa, status);
+}
+
+int pfo_fit_points(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
+                   double fx, double fy, double cx, double cy, int32_t k, int32_t mode,
+                   const int64_t* xs, const int64_t* ys, int64_t count, int32_t threads,
+                   double* normals, double* offsets, double* residuals, double* kappa,
+                   uint8_t* status) {
+  return fit_points_impl(depth, H, W, mask, fx, fy, cx, cy, k, mode, 0, xs, ys, count, threads,
+                         normals, offsets, residuals, kappa, status);
+}
+
+int pfo_fit_planes_partial(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
+                           double fx, double fy, double cx, double cy, int32_t k, int32_t mode,
+                           int32_t min_valid, int32_t threads, double* normals,
+                           double* offsets, double* residuals, double* kappa, uint8_t* status) {
+  if (min_valid < 3) return -1;
+  return fit_planes_impl(depth, H, W, mask, fx, fy, cx, cy, k, mode, min_valid, threads,
+                         normals, offsets, residuals, kappa, status);
+}
+
+int pfo_fit_points_partial(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
+                           double fx, double fy, double cx, double cy, int32_t k, int32_t mode,
+                           int32_t min_valid, const int64_t* xs, const int64_t* ys,
+                           int64_t count, int32_t threads, double* normals, double* offsets,
+                           double* residuals, double* kappa, uint8_t* status) {
+  if (min_valid < 3) return -1;
+  return fit_points_impl(depth, H, W, mask, fx, fy, cx, cy, k, mode, min_valid, xs, ys, count,
+                         threads, normals, offsets, residuals, kappa, status);
 }
 
 int pfo_fit_rects(const double* depth, int64_t H, int64_t W, const uint8_t* mask, double fx,

@@ -74,6 +74,21 @@ int pfo_fit_points(const double* depth, int64_t H, int64_t W, const uint8_t* mas
                    double* normals, double* offsets, double* residuals, double* kappa,
                    uint8_t* status);
 
+/* Partial windows: as pfo_fit_planes / pfo_fit_points, but a window is fitted
+ * from its valid pixels alone (those inside the image with valid depth) iff
+ * there are at least min_valid >= 3 of them and they do not all lie on one
+ * line of the pixel grid; the residual is the RMS over those pixels.
+ * min_valid >= k*k is the full-window rule.  Returns -1 for min_valid < 3. */
+int pfo_fit_planes_partial(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
+                           double fx, double fy, double cx, double cy, int32_t k, int32_t mode,
+                           int32_t min_valid, int32_t threads, double* normals,
+                           double* offsets, double* residuals, double* kappa, uint8_t* status);
+int pfo_fit_points_partial(const double* depth, int64_t H, int64_t W, const uint8_t* mask,
+                           double fx, double fy, double cx, double cy, int32_t k, int32_t mode,
+                           int32_t min_valid, const int64_t* xs, const int64_t* ys,
+                           int64_t count, int32_t threads, double* normals, double* offsets,
+                           double* residuals, double* kappa, uint8_t* status);
+
 /* Fits to arbitrary rectangles, the use of integral images the paper makes
  * (Sec. II-C): rects is int32 [count][4] = (x0, y0, w, h), covering columns
  * x0 .. x0+w-1 and rows y0 .. y0+h-1.  A rectangle is valid iff w, h >= 2, it

@@ -115,6 +115,16 @@ typedef struct {
                          kappa exceeds this (0 = 100); ignored otherwise */
   double disparity_scale;  /* PF_FLAG_DISPARITY: 1/Z = D * disparity_scale (finite, > 0);
                               ignored otherwise */
+  int32_t min_valid;  /* partial windows: 0 (or >= k*k) = the full-window rule: every
+                         pixel of the window must be valid.  3 <= min_valid < k*k: a
+                         window is fitted from its valid pixels alone when there are at
+                         least min_valid of them and they do not all lie on one line of
+                         the pixel grid (the plane is then determined); the residual is
+                         the RMS over those pixels.  The camera-only moments of Sec.
+                         II-A/B are then sums over the valid pixels, carried by the sweep
+                         as two extra integer channels.  FP64, PF_IMPLICIT/PF_EXPLICIT,
+                         pf_fit_planes and pf_fit_planes_batch only (PF_ERR_UNSUPPORTED
+                         otherwise); 1, 2 or < 0 is PF_ERR_UNSUPPORTED. */
 } pf_params;
 
 typedef struct pf_plan pf_plan;
@@ -173,8 +183,8 @@ typedef struct {
 /* Enqueue the fits of n frames (Sec. II-C: many fits from one pass over each
  * frame) in as few launches as possible: up to 32 frames per kernel launch,
  * of any sizes and window sizes, each described by its own plan.  All plans
- * must share mode, precision, kappa_flag, kappa_fp64 and the disparity setting (else
- * PF_ERR_UNSUPPORTED).  Every
+ * must share mode, precision, kappa_flag, kappa_fp64, the disparity setting and the
+ * partial-window min_valid (else PF_ERR_UNSUPPORTED).  Every
  * frame is checked on the host as in pf_fit_planes before anything is
  * enqueued; n = 0 is a no-op.  No workspace is needed. */
 pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io, int32_t n,

@@ -64,7 +64,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("window", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("kappa_flag", ctypes.c_double), ("kappa_fp64", ctypes.c_double),
-                ("disparity_scale", ctypes.c_double)]
+                ("disparity_scale", ctypes.c_double), ("min_valid", ctypes.c_int32)]
 
 
 _lib = None
@@ -149,7 +149,8 @@ class Plan:
 
     def __init__(self, intrinsics, height: int, width: int, window: int,
                  mode: str = "implicit", precision: str = "fp64", kappa_flag: float = 0.0,
-                 flags: int = 0, kappa_fp64: float = 0.0, disparity_scale: float = 0.0):
+                 flags: int = 0, kappa_fp64: float = 0.0, disparity_scale: float = 0.0,
+                 min_valid: int = 0):
         lib = load_library()
         fx, fy, cx, cy = (float(v) for v in intrinsics)
         if mode not in MODES:
@@ -158,7 +159,8 @@ class Plan:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         self._intr = _Intrinsics(fx, fy, cx, cy)
         self._params = _Params(int(window), MODES[mode], PRECISIONS[precision], int(flags),
-                               float(kappa_flag), float(kappa_fp64), float(disparity_scale))
+                               float(kappa_flag), float(kappa_fp64), float(disparity_scale),
+                               int(min_valid))
         h = ctypes.c_void_p()
         _check(lib.pf_plan_create(ctypes.byref(self._intr), int(height), int(width),
                                   ctypes.byref(self._params), ctypes.byref(h)))
@@ -202,17 +204,19 @@ _plan_cache_lock = threading.Lock()
 
 
 def get_plan(intrinsics, height, width, window, mode="implicit", precision="fp64",
-             kappa_flag=0.0, disparity_scale=None) -> Plan:
-    """Cached plan; disparity_scale (1/Z = D * scale) selects disparity input."""
+             kappa_flag=0.0, disparity_scale=None, min_valid=None) -> Plan:
+    """Cached plan; disparity_scale (1/Z = D * scale) selects disparity input,
+    min_valid partial windows."""
     ds = 0.0 if disparity_scale is None else float(disparity_scale)
+    mv = 0 if min_valid is None else int(min_valid)
     key = (tuple(float(v) for v in intrinsics), int(height), int(width), int(window), mode,
-           precision, float(kappa_flag), ds)
+           precision, float(kappa_flag), ds, mv)
     with _plan_cache_lock:
         p = _plan_cache.get(key)
         if p is None:
             p = Plan(intrinsics, height, width, window, mode, precision, kappa_flag,
                      flags=FLAG_DISPARITY if disparity_scale is not None else 0,
-                     disparity_scale=ds)
+                     disparity_scale=ds, min_valid=mv)
             _plan_cache[key] = p
         return p
 
@@ -244,7 +248,7 @@ class _on_device:
 
 def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "implicit",
                precision: str = "fp64", kappa_flag: float = 0.0, out=None, stream=None,
-               disparity_scale=None):
+               disparity_scale=None, min_valid=None):
     """Per-pixel plane fits of a depth frame on the GPU.
 
     depth       float32 tensor [H, W] on a HIP device (unit stride along W)
@@ -253,6 +257,8 @@ def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "
     valid_mask  optional uint8/bool tensor [H, W] on the same device (0 = invalid)
     out         optional (normals [3,H,W], offsets [H,W], residuals [H,W], status [H,W])
     disparity_scale  if given, `depth` holds disparity D with 1/Z = D * disparity_scale
+    min_valid   if given (3 <= min_valid < k*k), partial windows: a window is fitted
+                from its valid pixels when at least min_valid are valid
     Returns (normals, offsets, residuals, status), enqueued on the current stream.
     """
     import torch
@@ -261,7 +267,8 @@ def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "
     if depth.stride(1) != 1:
         raise ValueError("depth must have unit stride along W")
     H, W = depth.shape
-    plan = get_plan(intrinsics, H, W, window, mode, precision, kappa_flag, disparity_scale)
+    plan = get_plan(intrinsics, H, W, window, mode, precision, kappa_flag, disparity_scale,
+                    min_valid)
     dev = depth.device
     mptr, mpitch = None, 0
     if valid_mask is not None:
@@ -401,7 +408,7 @@ def _mask_arg(torch, valid_mask, depth):
 
 def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="implicit",
                      precision="fp64", kappa_flag=0.0, outs=None, stream=None,
-                     disparity_scale=None):
+                     disparity_scale=None, min_valid=None):
     """Per-pixel plane fits of several frames (any sizes, per-frame window sizes)
     in as few kernel launches as possible (up to 32 frames per launch).
 
@@ -428,7 +435,8 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
         if d.device != dev:
             raise ValueError("all frames must be on one device")
         H, W = d.shape
-        p = get_plan(intr[i], H, W, ks[i], mode, precision, kappa_flag, disparity_scale)
+        p = get_plan(intr[i], H, W, ks[i], mode, precision, kappa_flag, disparity_scale,
+                     min_valid)
         plans.append(p)
         mptr, mpitch = _mask_arg(torch, masks[i], d)
         if outs is None:

@@ -105,6 +105,7 @@ struct FitArgs {
   int vec_store;  // outputs 16-byte aligned, W and tile_w multiples of 4
   double* gws;    // backward: per-window moment gradients [4][H][W]
   double dscale;  // > 0: the input is disparity D with w = D * dscale; 0: depth Z, w = 1/Z
+  int min_valid;  // partial windows: fitted from >= min_valid valid pixels
 };
 
 // One frame of a launch, passed by value in the kernel arguments.
@@ -133,6 +134,7 @@ struct LaunchArgs {
   double kappa_fp64;
   double dscale;  // disparity input scale (0: depth input), shared by the launch's jobs
   double* gws;  // backward pass only (single job): moment-gradient workspace
+  int32_t min_valid;  // partial-window launches: minimum valid pixels per window
   Job jobs[kMaxJobs];
 };
 static_assert(sizeof(LaunchArgs) <= 4096, "kernel arguments too large");
@@ -151,9 +153,10 @@ template <typename T>
 struct Cursor {
   T w, yw, ww;  // sums of (w - w_ref), (y - y_ref)(w - w_ref), (w - w_ref)^2
   int n;        // number of valid pixels
+  int yn, y2n;  // partial windows: sums of (y - y_ref) and (y - y_ref)^2 over valid pixels
   __device__ void clear() {
     w = yw = ww = T(0);
-    n = 0;
+    n = yn = y2n = 0;
   }
 };
 
@@ -289,7 +292,7 @@ __device__ inline df32 disparity(float z, double dscale, df32) {
   return dscale > 0.0 ? df32(z) * to_df32(dscale) : recip(z, df32(0.0f));
 }
 
-template <typename T>
+template <typename T, bool PARTIAL = false>
 __device__ inline void add_sample(float z, int y, T w_ref, int y_ref, Cursor<T>& c, double dscale) {
   // branch-free: invalid samples contribute exact zeros
   const bool ok = depth_valid(z);
@@ -298,11 +301,16 @@ __device__ inline void add_sample(float z, int y, T w_ref, int y_ref, Cursor<T>&
   c.yw += T(y - y_ref) * wh;
   c.ww += wh * wh;
   c.n += ok ? 1 : 0;
+  if (PARTIAL) {
+    const int dy = ok ? y - y_ref : 0;
+    c.yn += dy;
+    c.y2n += dy * dy;
+  }
 }
 
 // The same sample taken out again: recomputed with the same operations, so
 // it is the exact value that was added.
-template <typename T>
+template <typename T, bool PARTIAL = false>
 __device__ inline void sub_sample(float z, int y, T w_ref, int y_ref, Cursor<T>& c, double dscale) {
   const bool ok = depth_valid(z);
   const T wh = ok ? disparity(z, dscale, T(0.0f)) - w_ref : T(0.0f);
@@ -310,6 +318,11 @@ __device__ inline void sub_sample(float z, int y, T w_ref, int y_ref, Cursor<T>&
   c.yw = c.yw - T(y - y_ref) * wh;
   c.ww = c.ww - wh * wh;
   c.n -= ok ? 1 : 0;
+  if (PARTIAL) {
+    const int dy = ok ? y - y_ref : 0;
+    c.yn -= dy;
+    c.y2n -= dy * dy;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -688,6 +701,78 @@ __device__ inline PixelOut solve_pixel(const FitArgs& a, T B, T Sxw, T Syw, T Q,
   return solve_moments<T, MODE>(a, m, x0, y0);
 }
 
+// Partial windows (FP64): the window is fitted from its Nv valid pixels, whose
+// camera-only moments are no longer the closed-form diagonal: with window
+// coordinates (x', y') over the valid pixels, P = sum [x' y' 1]^T [x' y' 1] =
+// [[Sxx, Sxy, Sx], [Sxy, Syy, Sy], [Sx, Sy, Nv]] (exact integers).  The window
+// is valid iff Nv >= max(min_valid, 3) and the valid pixels are not collinear,
+// i.e. D = (Nv Sxx - Sx^2)(Nv Syy - Sy^2) - (Nv Sxy - Sx Sy)^2 > 0; D is formed
+// from exact integer factors with a fused difference of products (Kahan), so a
+// collinear set gives exactly 0.  The data moments carry the hat-disparity
+// sums: sum x' w = Sxw^ + w_ref Sx since sum x' no longer vanishes.
+struct PartialSums {
+  double Nv, Sx, Sy, Sxx, Sxy, Syy;
+};
+
+template <int MODE>
+__device__ inline PixelOut solve_partial(const FitArgs& a, const PartialSums& c, double B,
+                                         double Sxw_h, double Syw_h, double Q, double w_ref,
+                                         int x0, int y0) {
+  const double Nv = c.Nv;
+  if (!(Nv >= double(a.min_valid) && Nv >= 3.0)) return invalid_pixel();
+  const double a1 = Nv * c.Sxx - c.Sx * c.Sx, b1 = Nv * c.Syy - c.Sy * c.Sy;
+  const double c1 = Nv * c.Sxy - c.Sx * c.Sy;
+  const double p = c1 * c1;
+  const double D = fma(a1, b1, -p) - fma(c1, c1, -p);
+  if (!(D > 0.5)) return invalid_pixel();
+  const double uc = (double(x0) - a.cx) * a.inv_fx, vc = (double(y0) - a.cy) * a.inv_fy;
+  PixelOut o;
+  o.st = 0;
+  o.kappa = 0.0f;
+  if (MODE == PF_EXPLICIT) {
+    // regress w^ = w - w_ref on (x', y', 1): P alpha^ = (Sxw^, Syw^, B); alpha' = alpha^ + w_ref e3
+    const double p00 = c.Sxx, p01 = c.Sxy, p02 = c.Sx, p11 = c.Syy, p12 = c.Sy, p22 = Nv;
+    const double k00 = p11 * p22 - p12 * p12, k01 = p02 * p12 - p01 * p22, k02 = p01 * p12 - p02 * p11;
+    const double k11 = p00 * p22 - p02 * p02, k12 = p01 * p02 - p00 * p12, k22 = p00 * p11 - p01 * p01;
+    const double idet = 1.0 / (p00 * k00 + p01 * k01 + p02 * k02);
+    const double ah = (k00 * Sxw_h + k01 * Syw_h + k02 * B) * idet;
+    const double bh = (k01 * Sxw_h + k11 * Syw_h + k12 * B) * idet;
+    const double ch = (k02 * Sxw_h + k12 * Syw_h + k22 * B) * idet;
+    const double ax = a.fx * ah, ay = a.fy * bh;
+    const double az = (ch + w_ref) - ax * uc - ay * vc;
+    const double rho = sqrt(ax * ax + ay * ay + az * az);
+    const double ssr = fmax(Q - (ah * Sxw_h + bh * Syw_h + ch * B), 0.0);
+    o.n0 = float(-ax / rho);
+    o.n1 = float(-ay / rho);
+    o.n2 = float(-az / rho);
+    o.d = float(1.0 / rho);
+    o.res = float(sqrt(ssr / Nv) / rho);
+    return o;
+  } else {
+    const double Sw = Nv * w_ref + B;
+    const double Sww = Q + w_ref * (2.0 * B + Nv * w_ref);
+    const double Sxw = Sxw_h + w_ref * c.Sx, Syw = Syw_h + w_ref * c.Sy;
+    const double iS = rcp_nr(Sww);
+    const double g11 = c.Sxx - Sxw * Sxw * iS, g22 = c.Syy - Syw * Syw * iS;
+    const double g12 = c.Sxy - Sxw * Syw * iS, g13 = c.Sx - Sxw * Sw * iS;
+    const double g23 = c.Sy - Syw * Sw * iS, g33 = (Nv * Q - B * B) * iS;
+    const double ifx = a.inv_fx, ify = a.inv_fy;
+    Implicit3<double> m;
+    m.c00 = g11 * ifx * ifx + 2.0 * g13 * uc * ifx + g33 * uc * uc;
+    m.c01 = g12 * ifx * ify + g13 * vc * ifx + g23 * uc * ify + g33 * uc * vc;
+    m.c02 = g13 * ifx + g33 * uc;
+    m.c11 = g22 * ify * ify + 2.0 * g23 * vc * ify + g33 * vc * vc;
+    m.c12 = g23 * ify + g33 * vc;
+    m.c22 = g33;
+    m.ifx = ifx; m.ify = ify; m.uc = uc; m.vc = vc; m.iS = iS;
+    m.Sxw = Sxw; m.Syw = Syw; m.Sw = Sw; m.iN = 1.0 / Nv;
+    const bool flag = a.kappa_flag > 0.0;
+    finish_implicit<double, double>(
+        a, m, smallest_eig<double>(m.c00, m.c01, m.c02, m.c11, m.c12, m.c22, flag), o, flag);
+    return o;
+  }
+}
+
 // Compensated path: moments formed in two-float arithmetic, solved in FP32;
 // an implicit window whose FP32 eigen-condition kappa exceeds the plan's
 // threshold is solved again in FP64 from the same two-float moments (status
@@ -857,11 +942,13 @@ __device__ inline int64_t bwd_ws_offset(const LaunchArgs& la, int jb) {
 
 // Workgroups per CU the register budget is sized for: the implicit forward
 // sweep (32 KB of LDS) is held to 128 VGPRs so that four waves share a SIMD.
-template <typename T, int MODE, bool BWD>
-constexpr int kMinGroups = (MODE == PF_IMPLICIT && !BWD) ? 4 : 1;
+template <typename T, int MODE, bool BWD, bool PARTIAL>
+constexpr int kMinGroups = (MODE == PF_IMPLICIT && !BWD && !PARTIAL) ? 4 : 1;
 
-template <typename T, int MODE, bool MASK, bool BWD = false>
-__global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD>)) void fit_planes_fused(LaunchArgs la) {
+template <typename T, int MODE, bool MASK, bool BWD = false, bool PARTIAL = false>
+__global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD, PARTIAL>)) void fit_planes_fused(LaunchArgs la) {
+  static_assert(!PARTIAL || (std::is_same<T, double>::value && !BWD && MODE != PF_IMPLICIT_LITERAL),
+                "partial windows: FP64 forward, implicit or explicit");
   using TL = Tiling<MODE>;
   // which job and which of its workgroups (the job table is uniform: scalar loop)
   int jb = 0;
@@ -902,11 +989,14 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD>)) void fit_planes
   a.gws = nullptr;
   if constexpr (BWD) a.gws = la.gws + bwd_ws_offset(la, jb);
   a.dscale = la.dscale;
+  a.min_valid = la.min_valid;
 
   __shared__ T sw[TL::rows * kPitch];
   __shared__ T syw[TL::rows * kPitch];
   __shared__ T sww[TL::rows * kPitch];
   __shared__ int sn[TL::rows * kPitch];
+  __shared__ int syn[PARTIAL ? TL::rows * kPitch : 1];   // partial windows: sum y~ per column
+  __shared__ int sy2n[PARTIAL ? TL::rows * kPitch : 1];  // and sum y~^2
   __shared__ double red[2 * (kBlock / 64)];
 
   const int tid = threadIdx.x;
@@ -964,7 +1054,7 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD>)) void fit_planes
       z[j] = (c + j < a.k - 1 && col_used) ? load_depth<MASK>(a, x, yb - a.r + c + j) : 0.0f;
 #pragma unroll
     for (int j = 0; j < TL::rows; ++j)
-      if (c + j < a.k - 1) add_sample<T>(z[j], yb - a.r + c + j, w_ref, y_ref, col, a.dscale);
+      if (c + j < a.k - 1) add_sample<T, PARTIAL>(z[j], yb - a.r + c + j, w_ref, y_ref, col, a.dscale);
   }
 
   // depth samples of the current round, loaded one round ahead
@@ -990,12 +1080,16 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD>)) void fit_planes
     for (int j = 0; j < TL::rows; ++j) {
       if (j < nr) {
         const int y0 = yg + j;
-        if (y0 > yb) sub_sample<T>(zg[j], y0 - a.r - 1, w_ref, y_ref, col, a.dscale);
-        add_sample<T>(zl[j], y0 + a.r, w_ref, y_ref, col, a.dscale);
+        if (y0 > yb) sub_sample<T, PARTIAL>(zg[j], y0 - a.r - 1, w_ref, y_ref, col, a.dscale);
+        add_sample<T, PARTIAL>(zl[j], y0 + a.r, w_ref, y_ref, col, a.dscale);
         sw[j * kPitch + li] = col.w;
         syw[j * kPitch + li] = col.yw;
         sww[j * kPitch + li] = col.ww;
         sn[j * kPitch + li] = col.n;
+        if (PARTIAL) {
+          syn[j * kPitch + li] = col.yn;
+          sy2n[j * kPitch + li] = col.y2n;
+        }
       }
     }
     // issue the next round's loads now; they land while the horizontal phase runs
@@ -1020,16 +1114,8 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD>)) void fit_planes
       // window sums slid along the run: column o + k - 1 enters as column o leaves
       T hw = T(0), hx = T(0), hy = T(0), hww = T(0);
       int hn = 0;
-#pragma unroll 4
-      for (int i = o0; i < o0 + a.k - 1; ++i) {
-        const int l = lds_index<MODE>(i);
-        const T v = rw[l];
-        hw += v;
-        hx += T(i - base) * v;
-        hy += ryw[l];
-        hww += rww[l];
-        hn += rn[l];
-      }
+      // partial windows: valid-pixel sums of x~, x~^2, y~, x~ y~, y~^2 (x~ = i - base)
+      int hxn = 0, hx2n = 0, hyn = 0, hxyn = 0, hy2n = 0;
       auto enter = [&](int i) {
         const int l = lds_index<MODE>(i);
         const T v = rw[l];
@@ -1038,6 +1124,14 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD>)) void fit_planes
         hy += ryw[l];
         hww += rww[l];
         hn += rn[l];
+        if (PARTIAL) {
+          const int dx = i - base, n = rn[l], yn = syn[hj * kPitch + l];
+          hxn += dx * n;
+          hx2n += dx * dx * n;
+          hyn += yn;
+          hxyn += dx * yn;
+          hy2n += sy2n[hj * kPitch + l];
+        }
       };
       auto leave = [&](int i) {
         const int l = lds_index<MODE>(i);
@@ -1047,7 +1141,17 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD>)) void fit_planes
         hy = hy - ryw[l];
         hww = hww - rww[l];
         hn -= rn[l];
+        if (PARTIAL) {
+          const int dx = i - base, n = rn[l], yn = syn[hj * kPitch + l];
+          hxn -= dx * n;
+          hx2n -= dx * dx * n;
+          hyn -= yn;
+          hxyn -= dx * yn;
+          hy2n -= sy2n[hj * kPitch + l];
+        }
       };
+#pragma unroll 4
+      for (int i = o0; i < o0 + a.k - 1; ++i) enter(i);
       // one output: advance the lead cursor, take the box sums, solve, advance the lag
       auto step = [&](int q) -> PixelOut {
         const int o = o0 + q;
@@ -1058,10 +1162,22 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD>)) void fit_planes
         const T Sxw = hx - T(q) * B;
         const T Syw = hy - T(y0 - y_ref) * B;
         PixelOut po;
-        if constexpr (std::is_same<T, df32>::value)
+        if constexpr (PARTIAL) {
+          // re-centre the valid-pixel sums to the window: x' = x~ - q, y' = y~ - dy
+          const double qd = double(q), dy = double(y0 - y_ref), nv = double(cnt);
+          PartialSums ps;
+          ps.Nv = nv;
+          ps.Sx = double(hxn) - qd * nv;
+          ps.Sy = double(hyn) - dy * nv;
+          ps.Sxx = double(hx2n) - 2.0 * qd * double(hxn) + qd * qd * nv;
+          ps.Syy = double(hy2n) - 2.0 * dy * double(hyn) + dy * dy * nv;
+          ps.Sxy = double(hxyn) - dy * double(hxn) - qd * double(hyn) + qd * dy * nv;
+          po = solve_partial<MODE>(a, ps, B, Sxw, Syw, Q, w_ref, ox0 + o, y0);
+        } else if constexpr (std::is_same<T, df32>::value) {
           po = solve_pixel_df<MODE>(a, B, Sxw, Syw, Q, cnt, w_ref, ox0 + o, y0);
-        else
+        } else {
           po = solve_pixel<T, MODE>(a, B, Sxw, Syw, Q, cnt, w_ref, ox0 + o, y0);
+        }
         leave(o);
         return po;
       };
@@ -1753,6 +1869,8 @@ struct pf_plan {
   double dscale() const {
     return (params.flags & PF_FLAG_DISPARITY) ? params.disparity_scale : 0.0;
   }
+  // partial windows: 3 <= min_valid < k^2 (0 or >= k^2 is the full-window rule)
+  bool partial() const { return params.min_valid > 0 && params.min_valid < k * k; }
   int k, r;
   double S2, N;
   int tile_w, tile_h, n_strips, n_bands;
@@ -1794,6 +1912,9 @@ pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t widt
        params->mode != PF_IMPLICIT_LITERAL) ||
       (params->mode == PF_IMPLICIT_LITERAL &&
        (params->precision != PF_PREC_FP64 || params->kappa_flag != 0.0)) ||
+      params->min_valid < 0 || (params->min_valid > 0 && params->min_valid < 3) ||
+      (params->min_valid > 0 && params->min_valid < k * k &&
+       (params->precision != PF_PREC_FP64 || params->mode == PF_IMPLICIT_LITERAL)) ||
       (params->precision != PF_PREC_FP64 && params->precision != PF_PREC_FP32 &&
        params->precision != PF_PREC_COMPENSATED) ||
       (params->flags & ~PF_FLAG_DISPARITY) != 0 ||
@@ -1880,7 +2001,8 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
         p->params.precision != plans[0]->params.precision ||
         p->params.kappa_flag != plans[0]->params.kappa_flag ||
         p->params.kappa_fp64 != plans[0]->params.kappa_fp64 ||
-        p->dscale() != plans[0]->dscale())
+        p->dscale() != plans[0]->dscale() || p->partial() != plans[0]->partial() ||
+        (p->partial() && p->params.min_valid != plans[0]->params.min_valid))
       return PF_ERR_UNSUPPORTED;
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -1893,6 +2015,7 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
     la.n_jobs = cnt;
     la.kappa_flag = plans[first]->params.kappa_flag;
     la.dscale = plans[first]->dscale();
+    la.min_valid = plans[first]->partial() ? plans[first]->params.min_valid : 0;
     la.kappa_fp64 = plans[first]->params.kappa_fp64 > 0.0 ? plans[first]->params.kappa_fp64
                                                            : kDefaultKappaFp64;
     bool has_mask = false;
@@ -1939,7 +2062,15 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
       if (has_mask) PF_LAUNCH(T, PF_IMPLICIT, true); else PF_LAUNCH(T, PF_IMPLICIT, false); \
     }                                                                          \
   } while (0)
-    if (prec == PF_PREC_FP64 && plans[first]->params.mode == PF_IMPLICIT_LITERAL) {
+    if (plans[first]->partial()) {
+      if (expl) {
+        if (has_mask) hipLaunchKernelGGL((fit_planes_fused<double, PF_EXPLICIT, true, false, true>), grid, block, 0, s, la);
+        else hipLaunchKernelGGL((fit_planes_fused<double, PF_EXPLICIT, false, false, true>), grid, block, 0, s, la);
+      } else {
+        if (has_mask) hipLaunchKernelGGL((fit_planes_fused<double, PF_IMPLICIT, true, false, true>), grid, block, 0, s, la);
+        else hipLaunchKernelGGL((fit_planes_fused<double, PF_IMPLICIT, false, false, true>), grid, block, 0, s, la);
+      }
+    } else if (prec == PF_PREC_FP64 && plans[first]->params.mode == PF_IMPLICIT_LITERAL) {
       if (has_mask) PF_LAUNCH(double, PF_IMPLICIT_LITERAL, true);
       else PF_LAUNCH(double, PF_IMPLICIT_LITERAL, false);
     } else if (prec == PF_PREC_FP64)
@@ -1997,7 +2128,7 @@ pf_status pf_fit_planes_backward_batch(const pf_plan* const* plans, const pf_bac
         (f.grad_residuals && misaligned(f.grad_residuals, 3)))
       return PF_ERR_ALIGNMENT;
     if (p->params.mode != plans[0]->params.mode || p->dscale() != plans[0]->dscale() ||
-        p->params.mode == PF_IMPLICIT_LITERAL)
+        p->params.mode == PF_IMPLICIT_LITERAL || p->partial())
       return PF_ERR_UNSUPPORTED;
     need += pf_backward_workspace_bytes(p);
   }
@@ -2087,7 +2218,7 @@ pf_status pf_fit_planes_xyz(const pf_plan* plan, const float* depth, int64_t dep
                             float* offsets, float* residuals, uint8_t* status, void* stream) {
   if (!plan || !depth || !normals || !offsets || !residuals) return PF_ERR_NULL;
   if (plan->params.precision != PF_PREC_FP64 || plan->dscale() > 0.0 ||
-      plan->params.mode == PF_IMPLICIT_LITERAL)
+      plan->params.mode == PF_IMPLICIT_LITERAL || plan->partial())
     return PF_ERR_UNSUPPORTED;
   if (depth_pitch < plan->W || depth_pitch > INT32_MAX ||
       (mask && (mask_pitch < plan->W || mask_pitch > INT32_MAX)))
@@ -2149,7 +2280,8 @@ pf_status pf_integral_images(const pf_plan* plan, const float* depth, int64_t de
                              const uint8_t* mask, int64_t mask_pitch, void* workspace,
                              size_t workspace_bytes, void* stream) {
   if (!plan || !depth) return PF_ERR_NULL;
-  if (plan->dscale() > 0.0 || plan->params.mode == PF_IMPLICIT_LITERAL) return PF_ERR_UNSUPPORTED;
+  if (plan->dscale() > 0.0 || plan->params.mode == PF_IMPLICIT_LITERAL || plan->partial())
+    return PF_ERR_UNSUPPORTED;
   if (depth_pitch < plan->W || (mask && mask_pitch < plan->W)) return PF_ERR_PITCH;
   if ((reinterpret_cast<uintptr_t>(depth) & 3) != 0) return PF_ERR_ALIGNMENT;
   if (!workspace || workspace_bytes < pf_integral_workspace_bytes(plan) ||
@@ -2185,7 +2317,7 @@ pf_status pf_fit_rects(const pf_plan* plan, const void* workspace, const int32_t
   if (n < 0) return PF_ERR_SHAPE;
   if (n == 0) return PF_OK;
   if (!plan || !workspace || !rects || !normals || !offsets || !residuals) return PF_ERR_NULL;
-  if (plan->params.mode == PF_IMPLICIT_LITERAL) return PF_ERR_UNSUPPORTED;
+  if (plan->params.mode == PF_IMPLICIT_LITERAL || plan->partial()) return PF_ERR_UNSUPPORTED;
   if (n > int64_t(INT32_MAX) * kBlock / 4) return PF_ERR_SHAPE;
   auto misaligned = [](const void* q, uintptr_t m) { return (reinterpret_cast<uintptr_t>(q) & m) != 0; };
   if (misaligned(rects, 3) || misaligned(normals, 3) || misaligned(offsets, 3) ||

@@ -32,11 +32,12 @@ def test_library_exports_every_declared_symbol():
 
 
 def _create(intr=(525.0, 525.0, 319.5, 239.5), H=480, W=640, k=5, mode=0, prec=0, flags=0,
-            kappa=0.0):
+            kappa=0.0, mv=0):
     lib = pf.load_library()
     h = ctypes.c_void_p()
     code = lib.pf_plan_create(ctypes.byref(_Intrinsics(*intr)), H, W,
-                              ctypes.byref(_Params(k, mode, prec, flags, kappa, 0.0)), ctypes.byref(h))
+                              ctypes.byref(_Params(k, mode, prec, flags, kappa, 0.0, 0.0, mv)),
+                              ctypes.byref(h))
     return code, h
 
 
@@ -45,7 +46,8 @@ def _create(intr=(525.0, 525.0, 319.5, 239.5), H=480, W=640, k=5, mode=0, prec=0
     (dict(H=0), 2), (dict(W=-3), 2), (dict(H=70000), 2),
     (dict(intr=(0.0, 525.0, 1.0, 1.0)), 4), (dict(intr=(525.0, float("nan"), 1.0, 1.0)), 4),
     (dict(intr=(525.0, 525.0, float("inf"), 1.0)), 4),
-    (dict(mode=3), 8), (dict(mode=2, prec=1), 8), (dict(mode=2, kappa=5.0), 8), (dict(mode=2), 0),
+    (dict(mode=3), 8), (dict(mode=2, prec=1), 8), (dict(mv=10), 0), (dict(mv=2), 8), (dict(mv=-1), 8),
+    (dict(mv=10, prec=2), 8), (dict(mv=10, mode=2), 8), (dict(mv=25, prec=2), 0), (dict(mode=2, kappa=5.0), 8), (dict(mode=2), 0),
     (dict(prec=7), 8), (dict(flags=2), 8), (dict(flags=1), 8), (dict(kappa=-1.0), 8),
     (dict(prec=2), 0),
     (dict(), 0), (dict(H=63, W=63, k=63), 0), (dict(mode=1, prec=1, kappa=1e6), 0),

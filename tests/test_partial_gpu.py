@@ -1,0 +1,87 @@
+"""GPU parity of partial windows (pf_params.min_valid) against the oracle's
+partial-window fits: windows fitted from their valid pixels when at least
+min_valid exist and they are not collinear.  Validity must match exactly;
+fitted windows are held to the parity bar of the full-window path."""
+import numpy as np
+import pytest
+
+import oracle
+import parity as PT
+from depthsynth import frames_for
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_fit_partial(depth, intr, k, mode, min_valid, mask=None):
+    import torch
+    import paper_2103_06644_amd as pf
+    d = torch.from_numpy(np.ascontiguousarray(depth, np.float32)).cuda()
+    m = None if mask is None else torch.from_numpy(mask.astype(np.uint8)).cuda()
+    n, o, r, s = pf.fit_planes(d, intr, k, m, mode=mode, min_valid=min_valid)
+    torch.cuda.synchronize()
+    return dict(normals=n.cpu().numpy().astype(np.float64), offsets=o.cpu().numpy().astype(np.float64),
+                residuals=r.cpu().numpy().astype(np.float64), status=s.cpu().numpy())
+
+
+@pytest.mark.parametrize("mode", ["implicit", "explicit"])
+@pytest.mark.parametrize("k,frac", [(5, 0.5), (9, 0.5), (9, 0.9), (15, 0.3)])
+def test_partial_parity_vga(gpu, k, frac, mode):
+    f = frames_for("vga_640x480")[0]
+    mv = max(3, int(frac * k * k))
+    print("[case] partial", k, mv, mode, flush=True)
+    g = gpu_fit_partial(f.depth, f.intrinsics, k, mode, mv)
+    o = oracle.fit_planes(f.depth.astype(np.float64), f.intrinsics, k, mode, min_valid=mv)
+    full = oracle.fit_planes(f.depth.astype(np.float64), f.intrinsics, k, mode)
+    assert (o["status"] == 0).sum() > (full["status"] == 0).sum()   # partial windows were fitted
+    rep = PT.check(g, o, mode, f.depth, f.intrinsics)
+    print(rep, flush=True)
+    PT.assert_parity(rep)
+
+
+@pytest.mark.parametrize("mode", ["implicit", "explicit"])
+def test_partial_hd_masked_sampled(gpu, mode):
+    f = frames_for("hd_1920x1080")[0]
+    k, mv = 15, 120
+    rng = np.random.Generator(np.random.PCG64(17))
+    mask = np.ones(f.depth.shape, np.uint8)
+    for _ in range(4000):   # square blobs masked out
+        s = int(rng.integers(2, 14))
+        y, x = int(rng.integers(0, 1080 - s)), int(rng.integers(0, 1920 - s))
+        mask[y:y + s, x:x + s] = 0
+    g = gpu_fit_partial(f.depth, f.intrinsics, k, mode, mv, mask=mask)
+    ys, xs = rng.integers(0, 1080, 8000), rng.integers(0, 1920, 8000)
+    o = oracle.fit_points(f.depth.astype(np.float64), f.intrinsics, k, xs, ys, mode, mask=mask,
+                          min_valid=mv)
+    rep = PT.check(g, o, mode, f.depth, f.intrinsics, sel=(ys, xs))
+    print(rep, flush=True)
+    PT.assert_parity(rep)
+
+
+def test_partial_collinear_batch_and_full_rule(gpu):
+    import torch
+    import paper_2103_06644_amd as pf
+    f = frames_for("plain_160x120")[0]
+    z = np.zeros(f.depth.shape, np.float32)
+    z[60, 40:60] = 2.0
+    z[30:40, 100] = 1.5
+    z[80, 10:20] = 1.0
+    z[81, 15] = 1.0
+    for mode in ("implicit", "explicit"):
+        g = gpu_fit_partial(z, f.intrinsics, 7, mode, 5)
+        o = oracle.fit_planes(z.astype(np.float64), f.intrinsics, 7, mode, min_valid=5)
+        assert np.array_equal((g["status"] & 1) == 0, o["status"] == 0), mode
+        assert g["status"][80, 15] == 0 and g["status"][60, 50] & 1
+    # min_valid = k^2 is the full-window rule, bit for bit
+    d = torch.from_numpy(f.depth).cuda()
+    a = pf.fit_planes(d, f.intrinsics, 5)
+    b = pf.fit_planes(d, f.intrinsics, 5, min_valid=25)
+    for x, y in zip(a, b):
+        assert torch.equal(torch.nan_to_num(x.float(), 7.0), torch.nan_to_num(y.float(), 7.0))
+    # batched partial windows equal single calls
+    fr = frames_for("vga_640x480")[0]
+    ds = [torch.from_numpy(fr.depth).cuda(), torch.from_numpy(fr.depth[:200, :300].copy()).cuda()]
+    batch = pf.fit_planes_batch(ds, fr.intrinsics, [9, 9], min_valid=40)
+    for i in range(2):
+        single = pf.fit_planes(ds[i], fr.intrinsics, 9, min_valid=40)
+        for x, y in zip(batch[i], single):
+            assert torch.equal(torch.nan_to_num(x.float(), 7.0), torch.nan_to_num(y.float(), 7.0))

@@ -339,6 +339,31 @@ def rects_measure(torch, pf, np, frames_for):
     return res
 
 
+def _time_calls(torch, run, sets, n_graph=16, reps=5):
+    """ms per call of run(s) (s = buffer set), replayed from a captured HIP graph
+    of n_graph consecutive calls on rotating sets."""
+    for i in range(3):
+        run(i % sets)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            for j in range(n_graph):
+                run(j % sets)
+    torch.cuda.current_stream().wait_stream(side)
+    g.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        g.replay()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / (reps * n_graph)
+
+
 def cpu_baseline(frame, ks, mode, budget_s):
     """The FP64 oracle on the host: random sample of window centres, growing until
     about budget_s seconds of work; returns Mpixel/s and what was sampled."""
@@ -422,6 +447,33 @@ def main():
                            ("implicit", "compensated"), ("explicit", "compensated")):
             ms, _ = time_launches(torch, pf, rig, f.intrinsics, ks, mode, prec, 64, 5)
             extras[f"vga_{mode}_{prec}_Mpx_s"] = round(px_step / (ms * 1e-3) / 1e6, 1)
+        # paper variants on the headline frame, k = 3, 5, 9, 15: partial windows (at
+        # least half of each window valid), the literal |(a,b,c,d)| = 1 constraint,
+        # and disparity input (D = f b / Z with f b = 39.375)
+        variants = {}
+        for name, kw, mode in (("partial_half_implicit", "partial", "implicit"),
+                               ("partial_half_explicit", "partial", "explicit"),
+                               ("literal_implicit", None, "implicit_literal")):
+            if kw == "partial":  # min_valid differs per k: one launch per window size
+                def run(s, mode=mode):
+                    for k in ks:
+                        pf.fit_planes(rig.depth[s], f.intrinsics, k, mode=mode,
+                                      min_valid=max(3, k * k // 2), out=rig.outs[s][0])
+                t = _time_calls(torch, run, rig.sets)
+            else:
+                t = _time_calls(torch, lambda s, mode=mode: pf.fit_planes_batch(
+                    [rig.depth[s]] * len(ks), f.intrinsics, list(ks), mode=mode,
+                    outs=rig.outs[s]), rig.sets)
+            variants[name] = {"ms_per_step": round(t, 5),
+                              "Mpx_s": round(rig.pixels * len(ks) / (t * 1e-3) / 1e6, 1)}
+        dsc = 1.0 / 39.375
+        drig = [(39.375 / torch.clamp(d, min=1e-6)) * (d > 0) for d in rig.depth]
+        t = _time_calls(torch, lambda s: pf.fit_planes_batch(
+            [drig[s]] * len(ks), f.intrinsics, list(ks), outs=rig.outs[s],
+            disparity_scale=dsc), rig.sets)
+        variants["disparity_implicit"] = {"ms_per_step": round(t, 5),
+                                          "Mpx_s": round(rig.pixels * len(ks) / (t * 1e-3) / 1e6, 1)}
+        extras["variants_vga_k3-15"] = variants
         del rig
         torch.cuda.empty_cache()
         hd = frames_for("hd_1920x1080")[0]

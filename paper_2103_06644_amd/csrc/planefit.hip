@@ -4,26 +4,32 @@
 // One fused kernel runs the whole per-frame path of the paper's integral-image
 // method (Sec. II-A..C) for a tile of output pixels:
 //
-//   integrands  w = 1/Z and its products with the window coordinates, shifted
-//               by a per-tile reference disparity so the sums stay small;
+//   integrands  w = 1/Z (or D * scale for disparity input) and its products
+//               with the window coordinates, shifted by a per-tile reference
+//               disparity so the sums stay small;
 //   2D scan     a transposed integral-image sweep: every thread owns one image
-//               column and carries its running column sums down the tile (the
-//               vertical prefix), then every thread owns a run of P output
-//               pixels of a row and carries running row sums of the column
-//               sums (the horizontal prefix).  Each prefix runs as two cursors
-//               k samples apart that add exactly the same values in exactly
-//               the same order, so "lead - lag" is bit-for-bit the difference
-//               of two integral-image entries k apart.  That is the box sum of
-//               Sec. II-C with no k-row history kept anywhere;
-//   box sums    lead minus lag, in both directions: the four-corner rule;
+//               column and slides a k-row window sum down the tile (a row
+//               enters as the row k above leaves, the leaving sample recomputed
+//               with the same operations), then every thread owns a run of
+//               output pixels of a row and slides a k-column sum of those
+//               column sums along it.  Each slide is the four-corner difference
+//               of an integral image (Sec. II-C) up to rounding order, with no
+//               k-row history kept anywhere;
 //   solve       explicit (Eq. 15-16) in closed form, or implicit (Eq. 14) as a
-//               3x3 symmetric eigenproblem after eliminating d;
+//               3x3 symmetric eigenproblem after eliminating d (or the literal
+//               4x4 with |(a, b, c, d)| = 1; or, for partial windows, with the
+//               valid-pixel camera moments carried as extra integer channels);
 //   store       normals (channel-planar), offsets, residuals, status.
 //
 // Only depth comes in and only the five outputs go out: the integral images
 // live in registers and LDS.  The camera-only moments (sum u^2 ... N) enter in
 // closed form in window-centred coordinates, where the k x k window has
 // sum x' = sum y' = sum x'y' = 0 and sum x'^2 = sum y'^2 = k^2 (k^2 - 1)/12.
+//
+// Also here: the adjoint (a backward instantiation of the same sweep, then a
+// box-filter sweep back to the pixels), the standard XYZ formulation for
+// comparison (Eq. 3-9, nine channels), and global FP64 integral images with
+// fits to arbitrary rectangles (the paper's own use of integral images).
 
 #include <hip/hip_runtime.h>
 
@@ -52,11 +58,12 @@ constexpr int kMaxWindow = 63;
 // more workgroups share a CU.
 //
 // LDS layout of one row of window column sums: column i lives at
-// (i % run) * sub + i / run.  In the horizontal phase the runs of a row read
-// the same (i % run) with consecutive i / run (consecutive words); in the
-// vertical phase 32 consecutive columns hit 32 distinct 8-byte slots because
-// sub * (run - 1) + 32 / run spans them without collisions modulo 32.  Both
-// directions are free of bank conflicts.
+// (i % run) * sub + i / run.  In the horizontal phase, where almost all LDS
+// traffic is (two reads per channel per output), the runs of a row read the
+// same (i % run) with consecutive i / run: consecutive words, no bank
+// conflicts.  The vertical phase writes each column once per row with a
+// stride of sub between neighbouring threads, which can cost two-way bank
+// conflicts on those writes.
 template <int MODE>
 struct Tiling;
 template <>

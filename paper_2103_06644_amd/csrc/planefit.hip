@@ -2027,9 +2027,19 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
                                                            : kDefaultKappaFp64;
     bool has_mask = false;
     int32_t wg = 0;
+    // dispatch order (implicit solves): the jobs with the longest workgroups
+    // (largest window, whose warm-up is longest) first, so that the launch's
+    // last, partial round of workgroups holds the shortest ones.  Measured +4 %
+    // on a 640x480 frame at k = 3..15 implicit, -2 % explicit (kept in order).
+    // Results do not depend on the order.
+    int32_t order[kMaxJobs];
+    for (int32_t j = 0; j < cnt; ++j) order[j] = first + j;
+    if (!expl)
+      std::stable_sort(order, order + cnt,
+                       [&](int32_t x, int32_t y) { return plans[x]->k > plans[y]->k; });
     for (int32_t j = 0; j < cnt; ++j) {
-      const pf_plan* p = plans[first + j];
-      const pf_frame_io& f = io[first + j];
+      const pf_plan* p = plans[order[j]];
+      const pf_frame_io& f = io[order[j]];
       Job& jb = la.jobs[j];
       jb.depth = f.depth;
       jb.mask = f.mask;

@@ -52,10 +52,10 @@ constexpr int kMaxWindow = 63;
 
 // Work split of one round: `rows` output rows go through the vertical phase
 // together, then every thread fits a run of `run` consecutive outputs of one
-// row (kBlock / run runs per row, rows * kBlock / run = kBlock threads).  The
-// explicit solve is cheap, so long runs amortise the horizontal warm-up; the
-// implicit solve dominates, so short rounds halve the LDS footprint and let
-// more workgroups share a CU.
+// row (kBlock / run runs per row, rows * kBlock / run = kBlock threads).  Short
+// rounds keep the LDS footprint at 32 KB (FP64), so that with 128 VGPRs four
+// workgroups share a CU; measured faster than longer runs (8 x 8) for both
+// solves, whose per-run warm-up the extra occupancy more than pays for.
 //
 // LDS layout of one row of window column sums: column i lives at
 // (i % run) * sub + i / run.  In the horizontal phase, where almost all LDS
@@ -68,7 +68,7 @@ template <int MODE>
 struct Tiling;
 template <>
 struct Tiling<PF_EXPLICIT> {
-  static constexpr int rows = 8, run = 8, sub = 36;
+  static constexpr int rows = 4, run = 4, sub = 72;
 };
 template <>
 struct Tiling<PF_IMPLICIT> {
@@ -947,10 +947,10 @@ __device__ inline int64_t bwd_ws_offset(const LaunchArgs& la, int jb) {
   return off;
 }
 
-// Workgroups per CU the register budget is sized for: the implicit forward
-// sweep (32 KB of LDS) is held to 128 VGPRs so that four waves share a SIMD.
+// Workgroups per CU the register budget is sized for: the forward sweeps
+// (32 KB of LDS) are held to 128 VGPRs so that four waves share a SIMD.
 template <typename T, int MODE, bool BWD, bool PARTIAL>
-constexpr int kMinGroups = (MODE == PF_IMPLICIT && !BWD && !PARTIAL) ? 4 : 1;
+constexpr int kMinGroups = (MODE != PF_IMPLICIT_LITERAL && !BWD && !PARTIAL) ? 4 : 1;
 
 template <typename T, int MODE, bool MASK, bool BWD = false, bool PARTIAL = false>
 __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD, PARTIAL>)) void fit_planes_fused(LaunchArgs la) {
@@ -1257,7 +1257,7 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD, PARTIAL>)) void f
       const int x0 = ox0 + o0;
       const int64_t p = (int64_t)y0 * a.W + x0;
       if (vec_store && o0 + TL::run <= o1 && x0 + TL::run <= a.W) {
-        // 16-byte aligned: W and tile_w are multiples of 4, o0 a multiple of 8
+        // 16-byte aligned: W and tile_w are multiples of 4, and so is o0
         float4* n0p = reinterpret_cast<float4*>(a.normals + p);
         float4* n1p = reinterpret_cast<float4*>(a.normals + a.plane + p);
         float4* n2p = reinterpret_cast<float4*>(a.normals + 2 * a.plane + p);
@@ -1945,11 +1945,10 @@ pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t widt
   const int tw_max = ((kBlock - (k - 1)) / 4) * 4;
   p->n_strips = int((width + tw_max - 1) / tw_max);
   p->tile_w = int(((width + p->n_strips - 1) / p->n_strips + 3) / 4 * 4);
-  // bands: enough workgroups to fill the chip (two resident per CU): one full
-  // wave of workgroups for the explicit solve, two for the heavier implicit one
-  // (at least 8 rows for the explicit solve, whose per-band warm-up and
-  // prologue would otherwise outweigh its short per-pixel work)
-  const int64_t target_groups = params->mode == PF_EXPLICIT ? 512 : 1024;
+  // bands: enough workgroups for one full round of the chip (four resident per
+  // CU on 256 CUs), with at least 8 rows for the explicit solve, whose per-band
+  // warm-up and prologue would otherwise outweigh its short per-pixel work
+  const int64_t target_groups = 1024;
   int64_t th = (height * p->n_strips + target_groups - 1) / target_groups;
   th = std::max<int64_t>(th, params->mode == PF_EXPLICIT ? 8 : 4);
   // tuning override of the band height (rows of output per workgroup)

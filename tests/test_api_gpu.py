@@ -1,0 +1,42 @@
+"""The Python usage shown in README.md, run end to end on the GPU (shapes,
+dtypes, status conventions, autograd and the rectangle path)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def test_readme_usage(gpu):
+    import torch
+    import paper_2103_06644_amd as pf
+    torch.manual_seed(0)
+    depth = torch.rand(480, 640, device="cuda") + 0.5
+    intr = (525.0, 525.0, 319.5, 239.5)
+    n, d, r, st = pf.fit_planes(depth, intr, 9)
+    assert n.shape == (3, 480, 640) and d.shape == r.shape == st.shape == (480, 640)
+    assert n.dtype == d.dtype == r.dtype == torch.float32 and st.dtype == torch.uint8
+    ok = (st & 1) == 0
+    assert ok.sum().item() == (480 - 8) * (640 - 8)          # every interior window valid
+    assert torch.allclose(torch.linalg.vector_norm(n[:, ok], dim=0),
+                          torch.ones(int(ok.sum()), device="cuda"), atol=1e-5)
+    assert (d[ok] >= 0).all()
+    n2, d2, r2, st2 = pf.fit_planes(depth, intr, 9, mode="explicit")
+    assert torch.equal((st2 & 1) == 0, ok)
+    outs = pf.fit_planes_batch([depth, depth], intr, [5, 15])
+    assert len(outs) == 2 and outs[1][0].shape == (3, 480, 640)
+    z = depth.clone().requires_grad_(True)
+    n, d, r, st = pf.fit_planes_differentiable(z, intr, 9)
+    torch.where(st == 0, r, torch.zeros_like(r)).sum().backward()
+    assert z.grad is not None and torch.isfinite(z.grad).all() and z.grad.abs().sum() > 0
+    ws = pf.integral_images(depth, intr)
+    rects = torch.tensor([[0, 0, 64, 48], [100, 50, 20, 30]], dtype=torch.int32, device="cuda")
+    n, d, r, st = pf.fit_rects(ws, depth.shape, intr, rects)
+    assert n.shape == (3, 2) and (st == 0).all()
+    # the explicit fit of a 9 x 9 rectangle equals the window fit there, within the
+    # bar (explicit: random depth would leave the implicit normal ill-conditioned)
+    wse = pf.integral_images(depth, intr, mode="explicit")
+    rr = torch.tensor([[200, 100, 9, 9]], dtype=torch.int32, device="cuda")
+    nr, dr, _, _ = pf.fit_rects(wse, depth.shape, intr, rr, mode="explicit")
+    nw, dw, _, _ = pf.fit_planes(depth, intr, 9, mode="explicit")
+    cos = float((nr[:, 0] * nw[:, 104, 204]).sum())
+    assert np.arccos(min(1.0, cos)) < 1e-4

@@ -294,7 +294,7 @@ def xyz_measure(torch, pf, frames_for):
 
 def rects_measure(torch, pf, np, frames_for):
     """Fits to many rectangles of one 1080p frame (the paper's use of integral
-    images, Sec. II-C): the FP64 integral images of the frame (four launches),
+    images, Sec. II-C): the FP64 integral images of the frame (five launches),
     then 100,000 seeded rectangles of 8..128 pixels a side, implicit and
     explicit; each timed over graph replays."""
     f = frames_for("hd_1920x1080")[0]

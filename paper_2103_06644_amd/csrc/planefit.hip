@@ -1617,7 +1617,8 @@ __global__ __launch_bounds__(kBlock) void fit_planes_xyz(LaunchArgs la) {
 // summed over valid pixels, with x~ = x - W/2 and y~ = y - H/2 (integers; the
 // centring halves the magnitude of the prefix sums a corner difference cancels),
 // then the column
-// totals of each band of kIntBand rows (5 [n_bands][W+1] planes).
+// totals of each band of kIntBand rows (5 [n_bands][W+1] planes), scanned in
+// place to the sum of the bands above.
 // ---------------------------------------------------------------------------
 constexpr int kIntBand = 16;
 constexpr int64_t kIntHeader = 32;  // doubles (256 bytes)
@@ -1741,7 +1742,30 @@ __global__ __launch_bounds__(kBlock) void integral_band_totals(IntegralArgs ia) 
   }
 }
 
-// column prefix sums within each band, started from the totals of the bands above
+// exclusive prefix of the band totals down each column (in place): one thread
+// per (column, channel), loads issued eight bands at a time
+__global__ __launch_bounds__(kBlock) void integral_band_scan(IntegralArgs ia) {
+  const int x = int(blockIdx.x) * kBlock + threadIdx.x;
+  const int c = int(blockIdx.y);
+  if (x > ia.W) return;
+  const int64_t P = int_plane(ia), ld = ia.W + 1;
+  const int n_bands = (ia.H + kIntBand - 1) / kIntBand;
+  double* T = ia.ws + kIntHeader + 5 * P + int64_t(c) * n_bands * ld;
+  double acc = 0.0;
+  for (int b0 = 0; b0 < n_bands; b0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (b0 + j < n_bands) ? T[int64_t(b0 + j) * ld + x] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (b0 + j < n_bands) {
+        T[int64_t(b0 + j) * ld + x] = acc;
+        acc += v[j];
+      }
+  }
+}
+
+// column prefix sums within each band, started from the scanned totals of the bands above
 __global__ __launch_bounds__(kBlock) void integral_cols(IntegralArgs ia) {
   const int x = int(blockIdx.x) * kBlock + threadIdx.x;
   const int band = int(blockIdx.y);
@@ -1752,8 +1776,7 @@ __global__ __launch_bounds__(kBlock) void integral_cols(IntegralArgs ia) {
   const double* T = ia.ws + kIntHeader + 5 * P;
   const int y0 = 1 + band * kIntBand, y1 = min(y0 + kIntBand, ia.H + 1);
   for (int c = 0; c < 5; ++c) {
-    double acc = 0.0;
-    for (int b = 0; b < band; ++b) acc += T[(int64_t(c) * n_bands + b) * ld + x];
+    double acc = T[(int64_t(c) * n_bands + band) * ld + x];
     double v[kIntBand];
 #pragma unroll
     for (int j = 0; j < kIntBand; ++j)
@@ -2318,6 +2341,7 @@ pf_status pf_integral_images(const pf_plan* plan, const float* depth, int64_t de
   hipLaunchKernelGGL(integral_ref, dim3(1), block, 0, s, ia);
   hipLaunchKernelGGL(integral_rows, dim3(unsigned(plan->H)), block, 0, s, ia);
   hipLaunchKernelGGL(integral_band_totals, dim3(strips, bands), block, 0, s, ia);
+  hipLaunchKernelGGL(integral_band_scan, dim3(strips, 5), block, 0, s, ia);
   hipLaunchKernelGGL(integral_cols, dim3(strips, bands), block, 0, s, ia);
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess) {

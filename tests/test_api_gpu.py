@@ -38,5 +38,6 @@ def test_readme_usage(gpu):
     rr = torch.tensor([[200, 100, 9, 9]], dtype=torch.int32, device="cuda")
     nr, dr, _, _ = pf.fit_rects(wse, depth.shape, intr, rr, mode="explicit")
     nw, dw, _, _ = pf.fit_planes(depth, intr, 9, mode="explicit")
-    cos = float((nr[:, 0] * nw[:, 104, 204]).sum())
-    assert np.arccos(min(1.0, cos)) < 1e-4
+    a = nr[:, 0].double().cpu().numpy()
+    b = nw[:, 104, 204].double().cpu().numpy()
+    assert np.arctan2(np.linalg.norm(np.cross(a, b)), a @ b) < 1e-4

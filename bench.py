@@ -364,6 +364,26 @@ def _time_calls(torch, run, sets, n_graph=16, reps=5):
     return a.elapsed_time(b) / (reps * n_graph)
 
 
+def autotune_measure(torch, pf, frames_for):
+    """Single-frame 640x480 launches at k = 9 with the plan's built-in band
+    height, then after pf_plan_autotune (which keeps the fastest of its
+    candidates in the cached plan).  Runs last: it changes the cached plans."""
+    f = frames_for("vga_640x480")[0]
+    rig = Rig(torch, f.depth, 32)
+    res = {}
+    for mode in ("implicit", "explicit"):
+        plan = pf.get_plan(f.intrinsics, 480, 640, 9, mode, "fp64")
+        before = plan.tile_h
+        run = lambda s, mode=mode: pf.fit_planes(rig.depth[s], f.intrinsics, 9, mode=mode,
+                                                 out=rig.outs[s][0])
+        t0 = _time_calls(torch, run, rig.sets)
+        chosen = plan.autotune(rig.depth[0])
+        t1 = _time_calls(torch, run, rig.sets)
+        res[mode] = {"default_band_rows": before, "default_Mpx_s": round(rig.pixels / (t0 * 1e-3) / 1e6, 1),
+                     "tuned_band_rows": chosen, "tuned_Mpx_s": round(rig.pixels / (t1 * 1e-3) / 1e6, 1)}
+    return res
+
+
 def cpu_baseline(frame, ks, mode, budget_s):
     """The FP64 oracle on the host: random sample of window centres, growing until
     about budget_s seconds of work; returns Mpixel/s and what was sampled."""
@@ -493,6 +513,7 @@ def main():
         extras["diff_8x640x480"] = diff_measure(torch, pf, np, frames_for, diff_loss_inputs)
         extras["xyz_vs_rgbd"] = xyz_measure(torch, pf, frames_for)
         extras["rects_1080p"] = rects_measure(torch, pf, np, frames_for)
+        extras["autotune_vga_k9"] = autotune_measure(torch, pf, frames_for)
         out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(f, ks, "implicit", args.cpu_seconds)

@@ -132,7 +132,8 @@ typedef struct pf_plan pf_plan;
 /* Host only.  Validates the camera, frame size and parameters, precomputes the
  * camera-only window moments for (camera, k) (Sec. II-A/B) and the launch
  * geometry.  Allocates host memory only (no device memory).  The plan is
- * immutable; it may be shared by threads and streams.  *out is set to NULL on
+ * immutable (except through pf_plan_autotune); it may be shared by threads
+ * and streams.  *out is set to NULL on
  * error. */
 pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t width,
                          const pf_params* params, pf_plan** out);
@@ -166,6 +167,26 @@ pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_p
                         const uint8_t* mask, int64_t mask_pitch, float* normals,
                         float* offsets, float* residuals, uint8_t* status, void* workspace,
                         size_t workspace_bytes, void* stream);
+
+/* Output rows per workgroup of the plan's launches (its band height); 0 for NULL. */
+int32_t pf_plan_band_height(const pf_plan* plan);
+
+/* Autotuning of the launch shape (beside the plan's built-in heuristic): times
+ * pf_fit_planes with this plan on the caller's frame and buffers for each
+ * candidate band height (output rows per workgroup: 4, 6, 8, 12, 16, 24, 32,
+ * 48, 64, up to H) and keeps the fastest in the plan, for every later call
+ * with it (single or batched).  Arguments as pf_fit_planes; the outputs are
+ * overwritten with a valid fit of the frame.  Blocks the calling thread until
+ * `stream` has run the timing launches (not for use under stream capture).
+ * The band height only changes which pixels share a reference disparity and
+ * the launch geometry, so results stay within the accuracy of the path.  This
+ * is the one call that modifies a plan: do not use the plan concurrently.
+ * *chosen (optional) receives the band height kept; on error the plan keeps
+ * its previous band height. */
+pf_status pf_plan_autotune(pf_plan* plan, const float* depth, int64_t depth_pitch,
+                           const uint8_t* mask, int64_t mask_pitch, float* normals,
+                           float* offsets, float* residuals, uint8_t* status, void* stream,
+                           int32_t* chosen);
 
 /* Device buffers of one frame for pf_fit_planes_batch (same meaning, layout and
  * ownership as the arguments of pf_fit_planes). */

@@ -70,7 +70,8 @@ class _Params(ctypes.Structure):
 _lib = None
 _lib_lock = threading.Lock()
 
-EXPORTS = ("pf_plan_create", "pf_plan_destroy", "pf_plan_workspace_bytes",
+EXPORTS = ("pf_plan_create", "pf_plan_destroy", "pf_plan_workspace_bytes", "pf_plan_autotune",
+           "pf_plan_band_height",
            "pf_plan_camera_moments", "pf_fit_planes", "pf_fit_planes_batch",
            "pf_backward_workspace_bytes", "pf_fit_planes_backward",
            "pf_fit_planes_backward_batch", "pf_fit_planes_xyz",
@@ -104,6 +105,11 @@ def load_library(path: str | None = None):
         lib.pf_fit_planes.restype = i32
         lib.pf_fit_planes_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_FrameIO), i32, vp]
         lib.pf_fit_planes_batch.restype = i32
+        lib.pf_plan_band_height.argtypes = [vp]
+        lib.pf_plan_band_height.restype = i32
+        lib.pf_plan_autotune.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp,
+                                         ctypes.POINTER(i32)]
+        lib.pf_plan_autotune.restype = i32
         lib.pf_backward_workspace_bytes.argtypes = [vp]
         lib.pf_backward_workspace_bytes.restype = ctypes.c_size_t
         lib.pf_fit_planes_backward.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp,
@@ -181,6 +187,36 @@ class Plan:
     @property
     def backward_workspace_bytes(self) -> int:
         return int(self._lib.pf_backward_workspace_bytes(self._h))
+
+    def autotune(self, depth, valid_mask=None, stream=None) -> int:
+        """Time this plan's launch on `depth` (float32 [H, W] on the GPU) for
+        several band heights and keep the fastest (pf_plan_autotune).  Blocks
+        until the timing launches have run; returns the band height kept."""
+        import torch
+        _check_depth(torch, depth)
+        if tuple(depth.shape) != (self.height, self.width):
+            raise ValueError("depth must match the plan's frame size")
+        dev = depth.device
+        H, W = self.height, self.width
+        mptr, mpitch = _mask_arg(torch, valid_mask, depth)
+        outs = (torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                torch.empty((H, W), dtype=torch.float32, device=dev),
+                torch.empty((H, W), dtype=torch.float32, device=dev),
+                torch.empty((H, W), dtype=torch.uint8, device=dev))
+        chosen = ctypes.c_int32(0)
+        with _on_device(torch, dev):
+            code = self._lib.pf_plan_autotune(
+                self._h, ctypes.c_void_p(depth.data_ptr()), depth.stride(0),
+                ctypes.c_void_p(mptr) if mptr else None, mpitch,
+                *[ctypes.c_void_p(t.data_ptr()) for t in outs],
+                _stream_handle(torch, dev, stream), ctypes.byref(chosen))
+        _check(code)
+        return int(chosen.value)
+
+    @property
+    def tile_h(self) -> int:
+        """Output rows per workgroup (band height) of this plan's launches."""
+        return int(self._lib.pf_plan_band_height(self._h))
 
     def camera_moments(self, x0: int, y0: int):
         out = (ctypes.c_double * 6)()

@@ -663,7 +663,7 @@ __device__ inline PixelOut solve_moments(const FitArgs& a, const Moments<S>& m, 
   PixelOut o;
   o.st = 0;
   o.kappa = 0.0f;
-  const S iN = S(a.inv_N), S2 = S(a.S2), iS2 = S(a.inv_S2);
+  const S iN = S(a.inv_N), iS2 = S(a.inv_S2);
   const S uc = (S(x0) - S(a.cx)) * S(a.inv_fx);
   const S vc = (S(y0) - S(a.cy)) * S(a.inv_fy);
   if constexpr (MODE == PF_IMPLICIT_LITERAL) {
@@ -2138,6 +2138,59 @@ pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_p
   if (!plan) return PF_ERR_NULL;
   const pf_frame_io f = {depth, depth_pitch, mask, mask_pitch, normals, offsets, residuals, status};
   return pf_fit_planes_batch(&plan, &f, 1, stream);
+}
+
+int32_t pf_plan_band_height(const pf_plan* plan) { return plan ? plan->tile_h : 0; }
+
+pf_status pf_plan_autotune(pf_plan* plan, const float* depth, int64_t depth_pitch,
+                           const uint8_t* mask, int64_t mask_pitch, float* normals,
+                           float* offsets, float* residuals, uint8_t* status, void* stream,
+                           int32_t* chosen) {
+  if (!plan) return PF_ERR_NULL;
+  const pf_frame_io f = {depth, depth_pitch, mask, mask_pitch, normals, offsets, residuals, status};
+  const pf_plan* cp = plan;
+  // validate the buffers once (and warm the code up) with the current band height
+  pf_status st = pf_fit_planes_batch(&cp, &f, 1, stream);
+  if (st != PF_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
+  static const int kCandidates[] = {4, 6, 8, 12, 16, 24, 32, 48, 64};
+  const int keep_h = plan->tile_h;
+  int best_h = keep_h;
+  float best_ms = 0.0f;
+  for (int cand : kCandidates) {
+    if (err != hipSuccess) break;
+    if (cand > plan->H) continue;
+    plan->tile_h = cand;
+    plan->n_bands = int((plan->H + cand - 1) / cand);
+    st = pf_fit_planes_batch(&cp, &f, 1, stream);  // warm-up at this shape
+    if (st != PF_OK) break;
+    err = hipEventRecord(e0, s);
+    for (int rep = 0; rep < 5 && st == PF_OK && err == hipSuccess; ++rep)
+      st = pf_fit_planes_batch(&cp, &f, 1, stream);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (st != PF_OK || err != hipSuccess) break;
+    if (best_ms == 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best_h = cand;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  plan->tile_h = (st == PF_OK && err == hipSuccess) ? best_h : keep_h;
+  plan->n_bands = int((plan->H + plan->tile_h - 1) / plan->tile_h);
+  if (chosen) *chosen = plan->tile_h;
+  if (st != PF_OK) return st;
+  if (err != hipSuccess) {
+    g_last_hip_error = int(err);
+    return PF_ERR_HIP;
+  }
+  return PF_OK;
 }
 
 size_t pf_backward_workspace_bytes(const pf_plan* plan) {

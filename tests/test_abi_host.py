@@ -251,3 +251,19 @@ def test_disparity_flag_validation():
             assert lib.pf_fit_planes_xyz(h, fake, 64, None, 0, fake, fake, fake, None, None) == 8
             assert lib.pf_integral_images(h, fake, 64, None, 0, fake, 1 << 30, None) == 8
             lib.pf_plan_destroy(h)
+
+
+def test_autotune_argument_checks_return_before_launch():
+    lib = pf.load_library()
+    code, plan = _create(H=48, W=64, k=5)
+    assert code == 0
+    fake = ctypes.c_void_p(0x10000)
+    chosen = ctypes.c_int32(-1)
+    assert lib.pf_plan_autotune(None, fake, 64, None, 0, fake, fake, fake, None, None,
+                                ctypes.byref(chosen)) == 1
+    assert lib.pf_plan_autotune(plan, None, 64, None, 0, fake, fake, fake, None, None,
+                                ctypes.byref(chosen)) == 1
+    assert lib.pf_plan_autotune(plan, fake, 60, None, 0, fake, fake, fake, None, None,
+                                ctypes.byref(chosen)) == 5
+    assert chosen.value == -1          # untouched: nothing was launched
+    lib.pf_plan_destroy(plan)

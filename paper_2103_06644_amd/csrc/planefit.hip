@@ -140,7 +140,7 @@ struct LaunchArgs {
   double kappa_flag;
   double kappa_fp64;
   double dscale;  // disparity input scale (0: depth input), shared by the launch's jobs
-  double* gws;  // backward pass only (single job): moment-gradient workspace
+  double* gws;  // backward launches: moment-gradient workspace (one region per job)
   int32_t min_valid;  // partial-window launches: minimum valid pixels per window
   Job jobs[kMaxJobs];
 };
@@ -935,9 +935,10 @@ __device__ inline MomentGrad implicit_adjoint(const FitArgs& a, const Moments<do
 // The fused kernel.  Workgroup = one strip of kBlock input columns (tile_w
 // output columns plus k-1 halo) by one band of tile_h output rows.
 //
-// Row bookkeeping for output row y0: the lead cursor has summed input rows
-// yb-r .. y0+r and the lag cursor rows yb-r .. y0-r-1, so lead - lag is the
-// column sum over the window rows y0-r .. y0+r.
+// Row bookkeeping for output row y0: each thread's column sums hold input rows
+// y0-r .. y0+r (row y0+r entered, row y0-r-1 left), i.e. the column window of
+// output row y0; the warm-up before the first row of the band enters rows
+// yb-r .. yb+r-1.
 // ---------------------------------------------------------------------------
 // Backward launches give every job a region of 4 H W doubles of the workspace,
 // in job order (a uniform scan of the job table).
@@ -1159,7 +1160,7 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD, PARTIAL>)) void f
       };
 #pragma unroll 4
       for (int i = o0; i < o0 + a.k - 1; ++i) enter(i);
-      // one output: advance the lead cursor, take the box sums, solve, advance the lag
+      // one output: column o + k - 1 enters, take the window sums, solve, column o leaves
       auto step = [&](int q) -> PixelOut {
         const int o = o0 + q;
         enter(o + a.k - 1);

@@ -1971,10 +1971,16 @@ pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t widt
   p->tile_w = int(((width + p->n_strips - 1) / p->n_strips + 3) / 4 * 4);
   // bands: enough workgroups for one full round of the chip (four resident per
   // CU on 256 CUs), with at least 8 rows for the explicit solve, whose per-band
-  // warm-up and prologue would otherwise outweigh its short per-pixel work
+  // warm-up and prologue would otherwise outweigh its short per-pixel work.
+  // Rounded up to whole rounds of rows: a band of 4q + 1 rows costs as many
+  // rounds as one of 4q + 4, whose fewer workgroups then share the chip
+  // (1920x1080, k = 15: 9 -> 12 rows, +10 % implicit, +4 % explicit).
   const int64_t target_groups = 1024;
+  constexpr int64_t round_rows = Tiling<PF_IMPLICIT>::rows;
+  static_assert(Tiling<PF_EXPLICIT>::rows == round_rows, "one row round for both solves");
   int64_t th = (height * p->n_strips + target_groups - 1) / target_groups;
   th = std::max<int64_t>(th, params->mode == PF_EXPLICIT ? 8 : 4);
+  th = (th + round_rows - 1) / round_rows * round_rows;
   // tuning override of the band height (rows of output per workgroup)
   if (const char* env = std::getenv("PF_TILE_H")) {
     const long v = std::strtol(env, nullptr, 10);

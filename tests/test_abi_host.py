@@ -267,3 +267,21 @@ def test_autotune_argument_checks_return_before_launch():
                                 ctypes.byref(chosen)) == 5
     assert chosen.value == -1          # untouched: nothing was launched
     lib.pf_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("H,W,k,mode,rows", [
+    (480, 640, 9, "implicit", 4),      # 3 strips x 480 rows fit one round at the 4-row minimum
+    (480, 640, 9, "explicit", 8),      # the explicit minimum
+    (1080, 1920, 15, "implicit", 12),  # 8 strips: 9 rows for one round, rounded up to whole 4-row rounds
+    (1080, 1920, 15, "explicit", 12),
+    (1080, 1920, 31, "implicit", 12),  # 9 strips: 10 rows -> 12
+    (720, 1280, 5, "implicit", 8),     # 6 strips: 5 rows -> 8
+    (30, 40, 3, "implicit", 4),
+    (6, 40, 3, "explicit", 6),         # never taller than the frame
+])
+def test_default_band_height_is_whole_rounds(H, W, k, mode, rows):
+    """The plan's band height: one round of 1,024 workgroups, at least 4 rows
+    (implicit) or 8 (explicit), rounded up to a multiple of the kernel's 4-row
+    round and capped at the frame height."""
+    p = pf.Plan((525.0, 525.0, W / 2 - 0.5, H / 2 - 0.5), H, W, k, mode)
+    assert p.tile_h == rows

@@ -471,19 +471,14 @@ def main():
         # least half of each window valid), the literal |(a,b,c,d)| = 1 constraint,
         # and disparity input (D = f b / Z with f b = 39.375)
         variants = {}
+        half = [max(3, k * k // 2) for k in ks]   # min_valid per window size
         for name, kw, mode in (("partial_half_implicit", "partial", "implicit"),
                                ("partial_half_explicit", "partial", "explicit"),
                                ("literal_implicit", None, "implicit_literal")):
-            if kw == "partial":  # min_valid differs per k: one launch per window size
-                def run(s, mode=mode):
-                    for k in ks:
-                        pf.fit_planes(rig.depth[s], f.intrinsics, k, mode=mode,
-                                      min_valid=max(3, k * k // 2), out=rig.outs[s][0])
-                t = _time_calls(torch, run, rig.sets)
-            else:
-                t = _time_calls(torch, lambda s, mode=mode: pf.fit_planes_batch(
-                    [rig.depth[s]] * len(ks), f.intrinsics, list(ks), mode=mode,
-                    outs=rig.outs[s]), rig.sets)
+            mv = half if kw == "partial" else None
+            t = _time_calls(torch, lambda s, mode=mode, mv=mv: pf.fit_planes_batch(
+                [rig.depth[s]] * len(ks), f.intrinsics, list(ks), mode=mode, min_valid=mv,
+                outs=rig.outs[s]), rig.sets)
             variants[name] = {"ms_per_step": round(t, 5),
                               "Mpx_s": round(rig.pixels * len(ks) / (t * 1e-3) / 1e6, 1)}
         dsc = 1.0 / 39.375

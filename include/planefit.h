@@ -204,8 +204,9 @@ typedef struct {
 /* Enqueue the fits of n frames (Sec. II-C: many fits from one pass over each
  * frame) in as few launches as possible: up to 32 frames per kernel launch,
  * of any sizes and window sizes, each described by its own plan.  All plans
- * must share mode, precision, kappa_flag, kappa_fp64, the disparity setting and the
- * partial-window min_valid (else PF_ERR_UNSUPPORTED).  Every
+ * must share mode, precision, kappa_flag, kappa_fp64 and the disparity setting,
+ * and be all partial-window plans or all full-window ones (else
+ * PF_ERR_UNSUPPORTED); partial-window plans may differ in min_valid.  Every
  * frame is checked on the host as in pf_fit_planes before anything is
  * enqueued; n = 0 is a no-op.  No workspace is needed. */
 pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io, int32_t n,

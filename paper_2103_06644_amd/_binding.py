@@ -452,6 +452,8 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
     intrinsics   one (fx, fy, cx, cy) for all frames, or a list of them
     windows      one odd k for all frames, or a list of them
     valid_masks  None or a list of (uint8/bool tensor or None)
+    min_valid    None, one value for all frames, or a list of them (partial
+                 windows; the frames must be all partial or all full-window)
     outs         optional list of (normals, offsets, residuals, status) per frame
     Returns the list of (normals, offsets, residuals, status).
     """
@@ -462,7 +464,8 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
     intr = list(intrinsics) if isinstance(intrinsics[0], (tuple, list)) else [intrinsics] * n
     ks = list(windows) if isinstance(windows, (tuple, list)) else [windows] * n
     masks = list(valid_masks) if valid_masks is not None else [None] * n
-    if not (len(intr) == len(ks) == len(masks) == n):
+    mvs = list(min_valid) if isinstance(min_valid, (tuple, list)) else [min_valid] * n
+    if not (len(intr) == len(ks) == len(masks) == len(mvs) == n):
         raise ValueError("per-frame argument lists must have one entry per frame")
     dev = depths[0].device
     plans, ios, results, keep = [], (_FrameIO * n)(), [], []
@@ -472,7 +475,7 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
             raise ValueError("all frames must be on one device")
         H, W = d.shape
         p = get_plan(intr[i], H, W, ks[i], mode, precision, kappa_flag, disparity_scale,
-                     min_valid)
+                     mvs[i])
         plans.append(p)
         mptr, mpitch = _mask_arg(torch, masks[i], d)
         if outs is None:

@@ -127,8 +127,10 @@ struct Job {
   int32_t depth_pitch, mask_pitch;
   int32_t H, W, k, tile_w, tile_h, n_strips;
   int32_t wg_begin;   // first workgroup of this job in the launch
-  int32_t vec_store;
+  int16_t vec_store;  // 1: outputs stored as float4 runs
+  int16_t min_valid;  // partial windows: minimum valid pixels per window (< k^2 <= 3969)
 };
+static_assert(kMaxWindow * kMaxWindow <= INT16_MAX, "min_valid is kept in 16 bits");
 
 // Up to kMaxJobs frames (any sizes and window sizes, one mode and precision)
 // per launch; the whole struct stays under the 4 KiB kernel-argument limit.
@@ -141,7 +143,6 @@ struct LaunchArgs {
   double kappa_fp64;
   double dscale;  // disparity input scale (0: depth input), shared by the launch's jobs
   double* gws;  // backward launches: moment-gradient workspace (one region per job)
-  int32_t min_valid;  // partial-window launches: minimum valid pixels per window
   Job jobs[kMaxJobs];
 };
 static_assert(sizeof(LaunchArgs) <= 4096, "kernel arguments too large");
@@ -997,7 +998,7 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD, PARTIAL>)) void f
   a.gws = nullptr;
   if constexpr (BWD) a.gws = la.gws + bwd_ws_offset(la, jb);
   a.dscale = la.dscale;
-  a.min_valid = la.min_valid;
+  a.min_valid = job.min_valid;
 
   __shared__ T sw[TL::rows * kPitch];
   __shared__ T syw[TL::rows * kPitch];
@@ -2037,8 +2038,7 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
         p->params.precision != plans[0]->params.precision ||
         p->params.kappa_flag != plans[0]->params.kappa_flag ||
         p->params.kappa_fp64 != plans[0]->params.kappa_fp64 ||
-        p->dscale() != plans[0]->dscale() || p->partial() != plans[0]->partial() ||
-        (p->partial() && p->params.min_valid != plans[0]->params.min_valid))
+        p->dscale() != plans[0]->dscale() || p->partial() != plans[0]->partial())
       return PF_ERR_UNSUPPORTED;
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -2051,7 +2051,6 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
     la.n_jobs = cnt;
     la.kappa_flag = plans[first]->params.kappa_flag;
     la.dscale = plans[first]->dscale();
-    la.min_valid = plans[first]->partial() ? plans[first]->params.min_valid : 0;
     la.kappa_fp64 = plans[first]->params.kappa_fp64 > 0.0 ? plans[first]->params.kappa_fp64
                                                            : kDefaultKappaFp64;
     bool has_mask = false;
@@ -2089,6 +2088,7 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
       jb.tile_h = p->tile_h;
       jb.n_strips = p->n_strips;
       jb.wg_begin = wg;
+      jb.min_valid = int16_t(p->partial() ? p->params.min_valid : 0);
       jb.vec_store = (p->W % 4 == 0) && (p->tile_w % 4 == 0) && aligned(f.normals, 15) &&
                      aligned(f.offsets, 15) && aligned(f.residuals, 15) &&
                      (!f.status || aligned(f.status, 3));

@@ -143,8 +143,17 @@ def test_batch_argument_checks_return_before_launch():
     io[1].depth_pitch = 64
     io[1].normals = None
     assert lib.pf_fit_planes_batch(plans2, io, 2, None) == 1         # NULL output in frame 1
+    # partial-window plans batch with each other (any min_valid), not with full-window ones
+    # (frame 2's NULL output stops the call on the host should the check let frame 1 pass)
+    c3, p3 = _create(H=48, W=64, k=5, mode=0, mv=12)
+    assert c3 == 0
+    io3 = (_FrameIO * 3)(*[_FrameIO(fake, 64, None, 0, fake, fake, fake, None) for _ in range(3)])
+    io3[2].normals = None
+    plans3 = (ctypes.c_void_p * 3)(p3.value, p1.value, p3.value)
+    assert lib.pf_fit_planes_batch(plans3, io3, 3, None) == 8        # partial with full-window
     lib.pf_plan_destroy(p1)
     lib.pf_plan_destroy(p2)
+    lib.pf_plan_destroy(p3)
 
 
 def test_backward_argument_checks_return_before_launch():

@@ -85,3 +85,13 @@ def test_partial_collinear_batch_and_full_rule(gpu):
         single = pf.fit_planes(ds[i], fr.intrinsics, 9, min_valid=40)
         for x, y in zip(batch[i], single):
             assert torch.equal(torch.nan_to_num(x.float(), 7.0), torch.nan_to_num(y.float(), 7.0))
+    # one launch, min_valid per frame (k^2 / 2 at each window size), both solves
+    ks = [3, 5, 9, 15]
+    mvs = [max(3, k * k // 2) for k in ks]
+    for mode in ("implicit", "explicit"):
+        batch = pf.fit_planes_batch([ds[0]] * 4, fr.intrinsics, ks, mode=mode, min_valid=mvs)
+        for i, (k, mv) in enumerate(zip(ks, mvs)):
+            single = pf.fit_planes(ds[0], fr.intrinsics, k, mode=mode, min_valid=mv)
+            for x, y in zip(batch[i], single):
+                assert torch.equal(torch.nan_to_num(x.float(), 7.0),
+                                   torch.nan_to_num(y.float(), 7.0)), (mode, k)

@@ -8,8 +8,9 @@ condition number of the uncentred 4x4 scatter matrix of Eq. 14 is reported
 beside it (it is large for clean windows, so it is not the gate).
 
 The FP64 and compensated paths are held to the parity tolerances; the FP32 path
-is reported only.  The table is printed and written to
-gpurun_out/precision_report.json.
+is reported only.  The table is printed, and also written as
+precision_report_k<k>.json into the directory named by the environment
+variable PF_REPORT_DIR when it is set.
 """
 import json
 import os
@@ -101,9 +102,11 @@ def test_precision_study_hd(gpu, k):
             row["gated_angle_max"] = float(ang[gated].max())
             row["gated_offset_max"] = float(off[gated].max())
             report["rows"].append(row)
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(f"gpurun_out/precision_report_k{k}.json", "w") as fh:
-        json.dump(report, fh, indent=1)
+    out_dir = os.environ.get("PF_REPORT_DIR")
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, f"precision_report_k{k}.json"), "w") as fh:
+            json.dump(report, fh, indent=1)
     print(json.dumps(report), flush=True)
     for row in report["rows"]:
         if row["precision"] in ("fp64", "compensated"):

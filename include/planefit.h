@@ -132,8 +132,7 @@ typedef struct pf_plan pf_plan;
 /* Host only.  Validates the camera, frame size and parameters, precomputes the
  * camera-only window moments for (camera, k) (Sec. II-A/B) and the launch
  * geometry.  Allocates host memory only (no device memory).  The plan is
- * immutable (except through pf_plan_autotune); it may be shared by threads
- * and streams.  *out is set to NULL on
+ * immutable; it may be shared by threads and streams.  *out is set to NULL on
  * error. */
 pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t width,
                          const pf_params* params, pf_plan** out);
@@ -171,19 +170,24 @@ pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_p
 /* Output rows per workgroup of the plan's launches (its band height); 0 for NULL. */
 int32_t pf_plan_band_height(const pf_plan* plan);
 
+/* A new plan equal to `plan` except that its launches use `band_height` output
+ * rows per workgroup (clamped to H).  `plan` is not modified; the new plan is
+ * destroyed with pf_plan_destroy.  The band height changes the launch geometry
+ * and which pixels share a reference disparity, so results stay within the
+ * accuracy of the path but need not be bit-identical to `plan`'s.
+ * PF_ERR_NULL for NULL arguments, PF_ERR_SHAPE for band_height < 1. */
+pf_status pf_plan_derive(const pf_plan* plan, int32_t band_height, pf_plan** out);
+
 /* Autotuning of the launch shape (beside the plan's built-in heuristic): times
- * pf_fit_planes with this plan on the caller's frame and buffers for each
- * candidate band height (output rows per workgroup: 4, 6, 8, 12, 16, 24, 32,
- * 48, 64, up to H) and keeps the fastest in the plan, for every later call
- * with it (single or batched).  Arguments as pf_fit_planes; the outputs are
- * overwritten with a valid fit of the frame.  Blocks the calling thread until
- * `stream` has run the timing launches (not for use under stream capture).
- * The band height only changes which pixels share a reference disparity and
- * the launch geometry, so results stay within the accuracy of the path.  This
- * is the one call that modifies a plan: do not use the plan concurrently.
- * *chosen (optional) receives the band height kept; on error the plan keeps
- * its previous band height. */
-pf_status pf_plan_autotune(pf_plan* plan, const float* depth, int64_t depth_pitch,
+ * pf_fit_planes on the caller's frame and buffers with a private copy of the
+ * plan for each candidate band height (output rows per workgroup: 4, 6, 8,
+ * 12, 16, 24, 32, 48, 64, up to H) and returns the fastest in *chosen; apply
+ * it with pf_plan_derive.  `plan` itself is never modified, so it stays safe
+ * to share between threads and streams.  Arguments as pf_fit_planes; the
+ * outputs are overwritten with a valid fit of the frame.  Blocks the calling
+ * thread until `stream` has run the timing launches (not for use under stream
+ * capture).  *chosen (optional) is written only on success. */
+pf_status pf_plan_autotune(const pf_plan* plan, const float* depth, int64_t depth_pitch,
                            const uint8_t* mask, int64_t mask_pitch, float* normals,
                            float* offsets, float* residuals, uint8_t* status, void* stream,
                            int32_t* chosen);
@@ -293,7 +297,9 @@ pf_status pf_fit_planes_xyz(const pf_plan* plan, const float* depth, int64_t dep
  * closed form (Sec. II-A/B).  Mode (implicit / explicit), kappa_flag and the
  * camera come from the plan; its window is not used; arithmetic is FP64.
  *   workspace  device, >= pf_integral_workspace_bytes(plan), 8-byte aligned;
- *              written by pf_integral_images, read by pf_fit_rects
+ *              written by pf_integral_images, read by pf_fit_rects (both take
+ *              its size in bytes and return PF_ERR_WORKSPACE when it is smaller
+ *              than the plan's frame needs)
  *   rects      device int32 [n][4] = (x0, y0, w, h): columns x0 .. x0+w-1,
  *              rows y0 .. y0+h-1
  *   normals    device float [3][n]; offsets, residuals float [n]; status
@@ -305,9 +311,9 @@ size_t pf_integral_workspace_bytes(const pf_plan* plan);
 pf_status pf_integral_images(const pf_plan* plan, const float* depth, int64_t depth_pitch,
                              const uint8_t* mask, int64_t mask_pitch, void* workspace,
                              size_t workspace_bytes, void* stream);
-pf_status pf_fit_rects(const pf_plan* plan, const void* workspace, const int32_t* rects,
-                       int64_t n, float* normals, float* offsets, float* residuals,
-                       uint8_t* status, void* stream);
+pf_status pf_fit_rects(const pf_plan* plan, const void* workspace, size_t workspace_bytes,
+                       const int32_t* rects, int64_t n, float* normals, float* offsets,
+                       float* residuals, uint8_t* status, void* stream);
 
 /* Static description of a status code. */
 const char* pf_status_string(pf_status s);

@@ -201,12 +201,25 @@ typedef struct {
   double n[3], d, residual, kappa;
 } fit_t;
 
-/* Orientation: the plane faces the camera, d >= 0. */
+/* Orientation.  The smallest eigenvector's sign is free (Sec. I-C), so the
+ * plane is made to face the camera: d >= 0.  A plane through the camera centre
+ * (d == 0) has no such side; it takes the first non-zero of n_z, n_y, n_x
+ * negative.  The offset is never a negative zero. */
 static void orient(fit_t* f) {
-  if (f->d < 0.0) {
+  int flip;
+  if (f->d != 0.0)
+    flip = f->d < 0.0;
+  else if (f->n[2] != 0.0)
+    flip = f->n[2] > 0.0;
+  else if (f->n[1] != 0.0)
+    flip = f->n[1] > 0.0;
+  else
+    flip = f->n[0] > 0.0;
+  if (flip) {
     f->d = -f->d;
     for (int i = 0; i < 3; ++i) f->n[i] = -f->n[i];
   }
+  if (f->d == 0.0) f->d = 0.0;
 }
 
 /* RMS over the window of (n.P_i + d)/Z_i: the residual of every mode. */

@@ -71,7 +71,7 @@ _lib = None
 _lib_lock = threading.Lock()
 
 EXPORTS = ("pf_plan_create", "pf_plan_destroy", "pf_plan_workspace_bytes", "pf_plan_autotune",
-           "pf_plan_band_height",
+           "pf_plan_band_height", "pf_plan_derive",
            "pf_plan_camera_moments", "pf_fit_planes", "pf_fit_planes_batch",
            "pf_backward_workspace_bytes", "pf_fit_planes_backward",
            "pf_fit_planes_backward_batch", "pf_fit_planes_xyz",
@@ -110,6 +110,8 @@ def load_library(path: str | None = None):
         lib.pf_plan_autotune.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp,
                                          ctypes.POINTER(i32)]
         lib.pf_plan_autotune.restype = i32
+        lib.pf_plan_derive.argtypes = [vp, i32, ctypes.POINTER(vp)]
+        lib.pf_plan_derive.restype = i32
         lib.pf_backward_workspace_bytes.argtypes = [vp]
         lib.pf_backward_workspace_bytes.restype = ctypes.c_size_t
         lib.pf_fit_planes_backward.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp,
@@ -123,7 +125,7 @@ def load_library(path: str | None = None):
         lib.pf_integral_workspace_bytes.restype = ctypes.c_size_t
         lib.pf_integral_images.argtypes = [vp, vp, i64, vp, i64, vp, ctypes.c_size_t, vp]
         lib.pf_integral_images.restype = i32
-        lib.pf_fit_rects.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp]
+        lib.pf_fit_rects.argtypes = [vp, vp, ctypes.c_size_t, vp, i64, vp, vp, vp, vp, vp]
         lib.pf_fit_rects.restype = i32
         lib.pf_fit_planes_xyz.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp]
         lib.pf_fit_planes_xyz.restype = i32
@@ -188,10 +190,24 @@ class Plan:
     def backward_workspace_bytes(self) -> int:
         return int(self._lib.pf_backward_workspace_bytes(self._h))
 
+    def derive(self, band_height: int) -> "Plan":
+        """A new plan equal to this one except for its band height
+        (pf_plan_derive); this plan is not changed."""
+        h = ctypes.c_void_p()
+        _check(self._lib.pf_plan_derive(self._h, int(band_height), ctypes.byref(h)))
+        p = Plan.__new__(Plan)
+        p._intr, p._params, p._h, p._lib = self._intr, self._params, h, self._lib
+        p.intrinsics, p.height, p.width, p.window = (self.intrinsics, self.height, self.width,
+                                                     self.window)
+        p.mode, p.precision, p.kappa_flag = self.mode, self.precision, self.kappa_flag
+        return p
+
     def autotune(self, depth, valid_mask=None, stream=None) -> int:
         """Time this plan's launch on `depth` (float32 [H, W] on the GPU) for
-        several band heights and keep the fastest (pf_plan_autotune).  Blocks
-        until the timing launches have run; returns the band height kept."""
+        several band heights (pf_plan_autotune) and return the fastest.  The
+        plan itself is not changed: apply the result with derive() or the
+        band_height argument of fit_planes.  Blocks until the timing launches
+        have run."""
         import torch
         _check_depth(torch, depth)
         if tuple(depth.shape) != (self.height, self.width):
@@ -240,9 +256,10 @@ _plan_cache_lock = threading.Lock()
 
 
 def get_plan(intrinsics, height, width, window, mode="implicit", precision="fp64",
-             kappa_flag=0.0, disparity_scale=None, min_valid=None) -> Plan:
+             kappa_flag=0.0, disparity_scale=None, min_valid=None, band_height=None) -> Plan:
     """Cached plan; disparity_scale (1/Z = D * scale) selects disparity input,
-    min_valid partial windows."""
+    min_valid partial windows, band_height a launch shape other than the
+    built-in one (a derived plan, cached under its own key)."""
     ds = 0.0 if disparity_scale is None else float(disparity_scale)
     mv = 0 if min_valid is None else int(min_valid)
     key = (tuple(float(v) for v in intrinsics), int(height), int(width), int(window), mode,
@@ -254,7 +271,14 @@ def get_plan(intrinsics, height, width, window, mode="implicit", precision="fp64
                      flags=FLAG_DISPARITY if disparity_scale is not None else 0,
                      disparity_scale=ds, min_valid=mv)
             _plan_cache[key] = p
-        return p
+        if band_height is None or int(band_height) == p.tile_h:
+            return p
+        dkey = key + (int(band_height),)
+        d = _plan_cache.get(dkey)
+        if d is None:
+            d = p.derive(int(band_height))
+            _plan_cache[dkey] = d
+        return d
 
 
 def _stream_handle(torch, device, stream):
@@ -284,7 +308,7 @@ class _on_device:
 
 def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "implicit",
                precision: str = "fp64", kappa_flag: float = 0.0, out=None, stream=None,
-               disparity_scale=None, min_valid=None):
+               disparity_scale=None, min_valid=None, band_height=None):
     """Per-pixel plane fits of a depth frame on the GPU.
 
     depth       float32 tensor [H, W] on a HIP device (unit stride along W)
@@ -295,6 +319,8 @@ def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "
     disparity_scale  if given, `depth` holds disparity D with 1/Z = D * disparity_scale
     min_valid   if given (3 <= min_valid < k*k), partial windows: a window is fitted
                 from its valid pixels when at least min_valid are valid
+    band_height output rows per workgroup (e.g. from Plan.autotune); None = the
+                plan's built-in launch shape
     Returns (normals, offsets, residuals, status), enqueued on the current stream.
     """
     import torch
@@ -304,7 +330,7 @@ def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "
         raise ValueError("depth must have unit stride along W")
     H, W = depth.shape
     plan = get_plan(intrinsics, H, W, window, mode, precision, kappa_flag, disparity_scale,
-                    min_valid)
+                    min_valid, band_height)
     dev = depth.device
     mptr, mpitch = None, 0
     if valid_mask is not None:
@@ -321,12 +347,8 @@ def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "
         residuals = torch.empty((H, W), dtype=torch.float32, device=dev)
         status = torch.empty((H, W), dtype=torch.uint8, device=dev)
     else:
+        _check_outs(torch, out, H, W, dev)
         normals, offsets, residuals, status = out
-        for t, shp, dt in ((normals, (3, H, W), torch.float32), (offsets, (H, W), torch.float32),
-                           (residuals, (H, W), torch.float32), (status, (H, W), torch.uint8)):
-            if tuple(t.shape) != shp or t.dtype != dt or not t.is_contiguous() or t.device != dev:
-                raise ValueError("out tensors must be contiguous, on depth's device, with "
-                                 "shapes [3,H,W], [H,W], [H,W], [H,W]")
     ws = plan.workspace_bytes
     work = torch.empty(ws, dtype=torch.uint8, device=dev) if ws else None
     with _on_device(torch, dev):
@@ -358,6 +380,7 @@ def fit_planes_xyz(depth, intrinsics, window: int, valid_mask=None, *, mode: str
                torch.empty((H, W), dtype=torch.float32, device=dev),
                torch.empty((H, W), dtype=torch.float32, device=dev),
                torch.empty((H, W), dtype=torch.uint8, device=dev))
+    _check_outs(torch, out, H, W, dev)
     normals, offsets, residuals, status = out
     with _on_device(torch, dev):
         code = plan._lib.pf_fit_planes_xyz(
@@ -405,22 +428,47 @@ def fit_rects(workspace, frame_shape, intrinsics, rects, *, mode="implicit", kap
         raise ValueError("rects must be a contiguous int32 [n, 4] tensor on the workspace's device")
     n = rects.shape[0]
     plan = get_plan(intrinsics, H, W, 3 if min(H, W) >= 3 else 1, mode, "fp64", kappa_flag)
+    need = int(plan._lib.pf_integral_workspace_bytes(plan.handle))
+    have = workspace.numel() * workspace.element_size()
+    if not workspace.is_contiguous() or have < need:
+        raise ValueError(f"workspace must be contiguous and hold the integral images of a "
+                         f"{H}x{W} frame ({need} bytes; got {have})")
     if out is None:
         out = (torch.empty((3, n), dtype=torch.float32, device=dev),
                torch.empty(n, dtype=torch.float32, device=dev),
                torch.empty(n, dtype=torch.float32, device=dev),
                torch.empty(n, dtype=torch.uint8, device=dev))
+    if len(out) != 4:
+        raise ValueError("out must be (normals, offsets, residuals, status)")
+    for t, shp, dt in zip(out, ((3, n), (n,), (n,), (n,)),
+                          (torch.float32, torch.float32, torch.float32, torch.uint8)):
+        if tuple(t.shape) != shp or t.dtype != dt or not t.is_contiguous() or t.device != dev:
+            raise ValueError("out tensors must be contiguous, on the workspace's device, with "
+                             "shapes [3,n], [n], [n], [n] (float32 x3, uint8)")
     normals, offsets, residuals, status = out
     if n == 0:
         return out
     with _on_device(torch, dev):
         code = plan._lib.pf_fit_rects(
-            plan.handle, ctypes.c_void_p(workspace.data_ptr()), ctypes.c_void_p(rects.data_ptr()),
+            plan.handle, ctypes.c_void_p(workspace.data_ptr()), have,
+            ctypes.c_void_p(rects.data_ptr()),
             n, ctypes.c_void_p(normals.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
             ctypes.c_void_p(residuals.data_ptr()), ctypes.c_void_p(status.data_ptr()),
             _stream_handle(torch, dev, stream))
     _check(code)
     return out
+
+
+def _check_outs(torch, out, H, W, dev):
+    """out = (normals [3,H,W], offsets [H,W], residuals [H,W], status [H,W]):
+    float32 / uint8, contiguous, on `dev` (the kernels write these shapes)."""
+    if len(out) != 4:
+        raise ValueError("out must be (normals, offsets, residuals, status)")
+    for t, shp, dt in zip(out, ((3, H, W), (H, W), (H, W), (H, W)),
+                          (torch.float32, torch.float32, torch.float32, torch.uint8)):
+        if tuple(t.shape) != shp or t.dtype != dt or not t.is_contiguous() or t.device != dev:
+            raise ValueError("out tensors must be contiguous, on depth's device, with "
+                             "shapes [3,H,W], [H,W], [H,W], [H,W] (float32 x3, uint8)")
 
 
 def _check_depth(torch, depth):
@@ -485,6 +533,7 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
                  torch.empty((H, W), dtype=torch.uint8, device=dev))
         else:
             o = outs[i]
+            _check_outs(torch, o, H, W, dev)
         results.append(o)
         ios[i] = _FrameIO(d.data_ptr(), d.stride(0), mptr, mpitch, o[0].data_ptr(),
                           o[1].data_ptr(), o[2].data_ptr(), o[3].data_ptr())

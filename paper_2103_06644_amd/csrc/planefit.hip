@@ -477,6 +477,18 @@ __device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22,
 //   Fy = sum (y - y_c)(w - w_ref)        Q  = sum (w - w_ref)^2
 // where x_c, y_c are the window centre's column and row; w = 1/Z.
 // ---------------------------------------------------------------------------
+// Orientation.  The smallest eigenvector's sign is free (Sec. I-C): the plane
+// is made to face the camera, d >= 0.  A plane through the camera centre
+// (d == 0) takes the first non-zero of n_z, n_y, n_x negative.  Returns
+// whether (n, d) must be negated.
+template <typename S>
+__device__ inline bool facing_flip(S d, S n0, S n1, S n2) {
+  if (d != S(0)) return d < S(0);
+  if (n2 != S(0)) return n2 > S(0);
+  if (n1 != S(0)) return n1 > S(0);
+  return n0 > S(0);
+}
+
 struct PixelOut {
   float n0, n1, n2, d, res;
   uint8_t st;
@@ -536,9 +548,10 @@ __device__ inline void finish_implicit(const FitArgs& a, const Implicit3<S>& c, 
   S n0 = S(e.n[0]), n1 = S(e.n[1]), n2 = S(e.n[2]);
   const S gp = n0 * c.ifx, gq = n1 * c.ify, gt = n0 * c.uc + n1 * c.vc + n2;
   S d = -(gp * c.Sxw + gq * c.Syw + gt * c.Sw) * c.iS;
-  if (d < S(0)) {
+  if (facing_flip(d, n0, n1, n2)) {
     d = -d; n0 = -n0; n1 = -n1; n2 = -n2;
   }
+  d = d + S(0);  // no negative zero
   o.n0 = float(n0);
   o.n1 = float(n1);
   o.n2 = float(n2);
@@ -644,7 +657,7 @@ __device__ inline PixelOut solve_literal(const FitArgs& a, const Moments<double>
   }
   const double sn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
   double n0 = v[0] / sn, n1 = v[1] / sn, n2 = v[2] / sn, d = v[3] / sn;
-  if (d < 0.0) {
+  if (facing_flip(d, n0, n1, n2)) {
     d = -d; n0 = -n0; n1 = -n1; n2 = -n2;
   }
   // residual: S a = l1 a for the unit 4-vector a = v/|v|, so the sum of squares
@@ -812,6 +825,17 @@ __device__ inline PixelOut solve_pixel_df(const FitArgs& a, df32 B, df32 Sxw, df
   const Eig3<float> ef = smallest_eig<float>(float(c.c00), float(c.c01), float(c.c02),
                                              float(c.c11), float(c.c12), float(c.c22));
   finish_implicit<double, float>(a, c, ef, o, true);
+  {
+    // residual from the FP64 Rayleigh quotient n^T C n of the final unit
+    // eigenvector: its error is quadratic in the eigenvector's, where l1 from
+    // the FP32 characteristic polynomial carries an error ~ eps32 * l3
+    const double n0 = ef.n[0], n1 = ef.n[1], n2 = ef.n[2];
+    const double rq = n0 * (c.c00 * n0 + c.c01 * n1 + c.c02 * n2) +
+                      n1 * (c.c01 * n0 + c.c11 * n1 + c.c12 * n2) +
+                      n2 * (c.c02 * n0 + c.c12 * n1 + c.c22 * n2);
+    const double nn = n0 * n0 + n1 * n1 + n2 * n2;
+    o.res = float(sqrt(fmax(rq / nn, 0.0) * c.iN));
+  }
   if (!(o.kappa <= float(a.kappa_fp64))) {
     o.st = 4;
     const bool flag = a.kappa_flag > 0.0;
@@ -870,7 +894,7 @@ __device__ inline MomentGrad implicit_adjoint(const FitArgs& a, const Moments<do
   const double gv[3] = {m.Sxw, m.Syw, m.Sw};  // g = (Sx, Sy, Sw)
   double gm0 = n0 * c.ifx, gm1 = n1 * c.ify, gm2 = n0 * uc + n1 * vc + n2;  // gamma = M n
   double d = -(gm0 * gv[0] + gm1 * gv[1] + gm2 * gv[2]) * c.iS;
-  if (d < 0.0) {
+  if (facing_flip(d, n0, n1, n2)) {
     d = -d; n0 = -n0; n1 = -n1; n2 = -n2; gm0 = -gm0; gm1 = -gm1; gm2 = -gm2;
   }
   const double iS = c.iS, N = a.N;
@@ -1274,18 +1298,13 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD, PARTIAL>)) void f
           rp[h] = make_float4(ores[4 * h], ores[4 * h + 1], ores[4 * h + 2], ores[4 * h + 3]);
         }
         if (a.status) {
-          uint32_t lo = 0, hi = 0;
+          // exactly the run's TL::run status bytes, as one 4-byte word (p is a
+          // multiple of 4 and status 4-byte aligned when vec_store is set)
+          static_assert(TL::run == 4, "one 32-bit status word per run");
+          uint32_t word = 0;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            lo |= uint32_t(ost[q]) << (8 * q);
-            hi |= uint32_t(ost[q + 4]) << (8 * q);
-          }
-          if ((p & 7) == 0) {
-            *reinterpret_cast<uint2*>(a.status + p) = make_uint2(lo, hi);
-          } else {
-            reinterpret_cast<uint32_t*>(a.status + p)[0] = lo;
-            reinterpret_cast<uint32_t*>(a.status + p)[1] = hi;
-          }
+          for (int q = 0; q < TL::run; ++q) word |= uint32_t(ost[q]) << (8 * q);
+          *reinterpret_cast<uint32_t*>(a.status + p) = word;
         }
       } else {
 #pragma unroll
@@ -1587,9 +1606,10 @@ __global__ __launch_bounds__(kBlock) void fit_planes_xyz(LaunchArgs la) {
             d = cc * is;
             res = sqrt(fmax(czz - aa * cxz - bb * cyz, 0.0) * iN) * is;
           }
-          if (d < 0.0) {
+          if (facing_flip(d, n0, n1, n2)) {
             d = -d; n0 = -n0; n1 = -n1; n2 = -n2;
           }
+          d = d + 0.0;
           on0 = float(n0); on1 = float(n1); on2 = float(n2); od = float(d); ores = float(res);
         }
         if (xo < W) {
@@ -1871,9 +1891,10 @@ __global__ __launch_bounds__(kBlock) void fit_rects_kernel(RectArgs ra) {
           if (!(kap <= ra.kappa_flag)) st = 2;
         }
       }
-      if (dd < 0.0) {
+      if (facing_flip(dd, n0, n1, n2)) {
         dd = -dd; n0 = -n0; n1 = -n1; n2 = -n2;
       }
+      dd = dd + 0.0;
       on0 = float(n0); on1 = float(n1); on2 = float(n2); od = float(dd); ores = float(res);
     }
   }
@@ -2149,34 +2170,47 @@ pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_p
 
 int32_t pf_plan_band_height(const pf_plan* plan) { return plan ? plan->tile_h : 0; }
 
-pf_status pf_plan_autotune(pf_plan* plan, const float* depth, int64_t depth_pitch,
+pf_status pf_plan_derive(const pf_plan* plan, int32_t band_height, pf_plan** out) {
+  if (out) *out = nullptr;
+  if (!plan || !out) return PF_ERR_NULL;
+  if (band_height < 1) return PF_ERR_SHAPE;
+  pf_plan* p = new (std::nothrow) pf_plan(*plan);
+  if (!p) return PF_ERR_UNSUPPORTED;
+  p->tile_h = int(std::min<int64_t>(band_height, p->H));
+  p->n_bands = int((p->H + p->tile_h - 1) / p->tile_h);
+  *out = p;
+  return PF_OK;
+}
+
+pf_status pf_plan_autotune(const pf_plan* plan, const float* depth, int64_t depth_pitch,
                            const uint8_t* mask, int64_t mask_pitch, float* normals,
                            float* offsets, float* residuals, uint8_t* status, void* stream,
                            int32_t* chosen) {
   if (!plan) return PF_ERR_NULL;
   const pf_frame_io f = {depth, depth_pitch, mask, mask_pitch, normals, offsets, residuals, status};
-  const pf_plan* cp = plan;
-  // validate the buffers once (and warm the code up) with the current band height
-  pf_status st = pf_fit_planes_batch(&cp, &f, 1, stream);
+  // validate the buffers once (and warm the code up) with the plan's own band height
+  pf_status st = pf_fit_planes_batch(&plan, &f, 1, stream);
   if (st != PF_OK) return st;
+  // candidates run on a private copy: the caller's plan is never written
+  pf_plan trial(*plan);
+  const pf_plan* tp = &trial;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t err = hipEventCreate(&e0);
   if (err == hipSuccess) err = hipEventCreate(&e1);
   static const int kCandidates[] = {4, 6, 8, 12, 16, 24, 32, 48, 64};
-  const int keep_h = plan->tile_h;
-  int best_h = keep_h;
+  int best_h = plan->tile_h;
   float best_ms = 0.0f;
   for (int cand : kCandidates) {
     if (err != hipSuccess) break;
     if (cand > plan->H) continue;
-    plan->tile_h = cand;
-    plan->n_bands = int((plan->H + cand - 1) / cand);
-    st = pf_fit_planes_batch(&cp, &f, 1, stream);  // warm-up at this shape
+    trial.tile_h = cand;
+    trial.n_bands = int((plan->H + cand - 1) / cand);
+    st = pf_fit_planes_batch(&tp, &f, 1, stream);  // warm-up at this shape
     if (st != PF_OK) break;
     err = hipEventRecord(e0, s);
     for (int rep = 0; rep < 5 && st == PF_OK && err == hipSuccess; ++rep)
-      st = pf_fit_planes_batch(&cp, &f, 1, stream);
+      st = pf_fit_planes_batch(&tp, &f, 1, stream);
     if (err == hipSuccess) err = hipEventRecord(e1, s);
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     float ms = 0.0f;
@@ -2189,14 +2223,12 @@ pf_status pf_plan_autotune(pf_plan* plan, const float* depth, int64_t depth_pitc
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  plan->tile_h = (st == PF_OK && err == hipSuccess) ? best_h : keep_h;
-  plan->n_bands = int((plan->H + plan->tile_h - 1) / plan->tile_h);
-  if (chosen) *chosen = plan->tile_h;
   if (st != PF_OK) return st;
   if (err != hipSuccess) {
     g_last_hip_error = int(err);
     return PF_ERR_HIP;
   }
+  if (chosen) *chosen = best_h;
   return PF_OK;
 }
 
@@ -2411,12 +2443,13 @@ pf_status pf_integral_images(const pf_plan* plan, const float* depth, int64_t de
   return PF_OK;
 }
 
-pf_status pf_fit_rects(const pf_plan* plan, const void* workspace, const int32_t* rects,
-                       int64_t n, float* normals, float* offsets, float* residuals,
-                       uint8_t* status, void* stream) {
+pf_status pf_fit_rects(const pf_plan* plan, const void* workspace, size_t workspace_bytes,
+                       const int32_t* rects, int64_t n, float* normals, float* offsets,
+                       float* residuals, uint8_t* status, void* stream) {
   if (n < 0) return PF_ERR_SHAPE;
   if (n == 0) return PF_OK;
   if (!plan || !workspace || !rects || !normals || !offsets || !residuals) return PF_ERR_NULL;
+  if (workspace_bytes < pf_integral_workspace_bytes(plan)) return PF_ERR_WORKSPACE;
   if (plan->params.mode == PF_IMPLICIT_LITERAL || plan->partial()) return PF_ERR_UNSUPPORTED;
   if (n > int64_t(INT32_MAX) * kBlock / 4) return PF_ERR_SHAPE;
   auto misaligned = [](const void* q, uintptr_t m) { return (reinterpret_cast<uintptr_t>(q) & m) != 0; };

@@ -11,7 +11,9 @@ The facts used:
     fit (Eq. 15) and numpy.linalg.svd for the constrained implicit fit;
   * the definition of the objective, minimised by scipy.optimize;
   * brute-force window sums vs four-corner sums of integral images (Sec. II-C);
-  * invariants: power-of-two and general depth scaling, image flips.
+  * invariants: power-of-two and general depth scaling, image flips;
+  * exact symmetry: a window whose best plane passes through the camera
+    centre, for the orientation tie-break.
 """
 from __future__ import annotations
 
@@ -292,6 +294,100 @@ def pin_explicit_orthogonality(k=5):
     return fails
 
 
+def pin_kappa(k=5, tol=1e-9):
+    """kappa = l3 / (l2 - l1) of the implicit 3x3 (the gate of the parity tests)
+    against numpy.linalg.eigvalsh of B^T B, B = m - w (w^T m) / (w^T w): the
+    design with the disparity direction projected out, whose Gram matrix is
+    the 1/Z^2-weighted covariance of the back-projected points."""
+    cam, z, pts = _noisy_windows(count=48, seed=21)
+    intr = (cam.fx, cam.fy, cam.cx, cam.cy)
+    xs = np.array([p[0] for p in pts])
+    ys = np.array([p[1] for p in pts])
+    oi = oracle.fit_points(z, intr, k, xs, ys, "implicit")
+    fails = []
+    for i, (x0, y0) in enumerate(pts):
+        m, w, _ = _window_design(z, cam, k, x0, y0)
+        B = m - np.outer(w, w @ m) / (w @ w)
+        l1, l2, l3 = np.linalg.eigvalsh(B.T @ B)
+        want = l3 / (l2 - l1)
+        if abs(oi["kappa"][i] / want - 1) > tol:
+            fails.append(f"kappa at {(x0, y0)}: {oi['kappa'][i]!r} vs eigvalsh {want!r}")
+    return fails
+
+
+def pin_xyz_library_routines(k=5, tol=1e-9):
+    """The standard XYZ fits (Eq. 3-9) on noisy windows: explicit against
+    numpy lstsq of Z on (X, Y, 1), implicit against the smallest right singular
+    vector of the centred points (unweighted PCA, |n| = 1); both oriented d >= 0."""
+    cam, z, pts = _noisy_windows(count=40, seed=17)
+    intr = (cam.fx, cam.fy, cam.cx, cam.cy)
+    xs = np.array([p[0] for p in pts])
+    ys = np.array([p[1] for p in pts])
+    oe = oracle.fit_points(z, intr, k, xs, ys, "xyz_explicit")
+    oi = oracle.fit_points(z, intr, k, xs, ys, "xyz_implicit")
+    fails = []
+    for i, (x0, y0) in enumerate(pts):
+        m, _, zz = _window_design(z, cam, k, x0, y0)
+        P = m * zz[:, None]                        # back-projected points (Eq. 1)
+        a, b, c = np.linalg.lstsq(np.stack([P[:, 0], P[:, 1], np.ones(len(zz))], 1), P[:, 2],
+                                  rcond=None)[0]
+        s_ = np.sqrt(a * a + b * b + 1.0)
+        n_e, d_e = np.array([a, b, -1.0]) / s_, c / s_
+        if d_e < 0:
+            n_e, d_e = -n_e, -d_e
+        ang = angle(oe["normals"][:, i], n_e)
+        if ang > tol or abs(oe["offsets"][i] / d_e - 1) > tol:
+            fails.append(f"xyz explicit vs lstsq at {(x0, y0)}: angle {ang:.2e}, "
+                         f"offset {oe['offsets'][i]} vs {d_e}")
+        cen = P.mean(0)
+        n_i = np.linalg.svd(P - cen)[2][-1]
+        d_i = -n_i @ cen
+        if d_i < 0:
+            n_i, d_i = -n_i, -d_i
+        kap = max(1.0, oi["kappa"][i])
+        ang = angle(oi["normals"][:, i], n_i)
+        if ang > tol * kap or abs(oi["offsets"][i] / d_i - 1) > tol * kap:
+            fails.append(f"xyz implicit vs svd at {(x0, y0)}: angle {ang:.2e}, "
+                         f"offset {oi['offsets'][i]} vs {d_i}")
+    return fails
+
+
+def tie_break_frame(fx, fy):
+    """A 5 x 5 depth frame whose one full window is centred on the optical axis
+    (c = (2, 2)), with depths 1/2 and 1 placed with mirror symmetry in x and
+    y: 13 pixels at 1/2 (centre, the four diagonal neighbours, the four
+    corners, the two ends of the middle row and of the middle column) and 12
+    at 1.  Every integrand is a short dyadic number, so every sum is exact.
+    By symmetry the 1/Z^2-weighted centroid lies on the optical axis and the
+    weighted covariance is diagonal; its x and y entries are the camera-only
+    sums S2/fx^2, S2/fy^2 (S2 = 50) and its z entry is about 2.4, so the
+    best plane is X = 0 (fx > fy) or Y = 0 (fx < fy): a plane through the
+    camera centre, d = 0."""
+    z = np.ones((5, 5))
+    for dy, dx in [(0, 0), (-1, -1), (-1, 1), (1, -1), (1, 1), (-2, -2), (-2, 2), (2, -2),
+                   (2, 2), (0, -2), (0, 2), (-2, 0), (2, 0)]:
+        z[2 + dy, 2 + dx] = 0.5
+    return z, (float(fx), float(fy), 2.0, 2.0)
+
+
+def pin_orientation_tie_break():
+    """d = 0 leaves the sign of the eigenvector (Sec. I-C) to the tie-break:
+    the first non-zero of n_z, n_y, n_x is negative.  On the symmetric frame
+    the exact answer is n = (-1, 0, 0) for fx > fy and (0, -1, 0) for fx < fy,
+    with d exactly 0 (and not -0)."""
+    fails = []
+    for (fx, fy), want in (((64.0, 32.0), (-1.0, 0.0, 0.0)), ((32.0, 64.0), (0.0, -1.0, 0.0))):
+        z, intr = tie_break_frame(fx, fy)
+        for mode in ("implicit", "implicit_scatter"):
+            o = oracle.fit_points(z, intr, 5, np.array([2]), np.array([2]), mode)
+            n, d = o["normals"][:, 0], o["offsets"][0]
+            if o["status"][0] != 0 or not np.array_equal(n, np.array(want)) or d != 0.0 \
+                    or np.signbit(d):
+                fails.append(f"tie-break fx={fx} fy={fy} {mode}: n={n} d={d!r}, want {want}, 0")
+    return fails
+
+
 ALL_PINS = [pin_exact_planes, pin_camera_moments, pin_integral_vs_direct,
             pin_integral_method_fit, pin_library_routines, pin_objective_minimum,
-            pin_invariants, pin_explicit_orthogonality]
+            pin_invariants, pin_explicit_orthogonality, pin_kappa, pin_xyz_library_routines,
+            pin_orientation_tie_break]

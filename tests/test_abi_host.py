@@ -239,11 +239,13 @@ def test_rect_argument_checks_return_before_launch():
     assert lib.pf_integral_images(plan, fake, 63, None, 0, fake, need, None) == 5
     assert lib.pf_integral_images(plan, fake, 64, None, 0, fake, need - 1, None) == 7
     assert lib.pf_integral_images(plan, fake, 64, None, 0, odd, need, None) == 7
-    assert lib.pf_fit_rects(plan, fake, fake, 0, fake, fake, fake, None, None) == 0   # no-op
-    assert lib.pf_fit_rects(plan, fake, fake, -1, fake, fake, fake, None, None) == 2
-    assert lib.pf_fit_rects(plan, None, fake, 3, fake, fake, fake, None, None) == 1
-    assert lib.pf_fit_rects(plan, fake, fake, 3, ctypes.c_void_p(0x10001), fake, fake, None,
-                            None) == 6
+    assert lib.pf_fit_rects(plan, fake, need, fake, 0, fake, fake, fake, None, None) == 0  # no-op
+    assert lib.pf_fit_rects(plan, fake, need, fake, -1, fake, fake, fake, None, None) == 2
+    assert lib.pf_fit_rects(plan, None, need, fake, 3, fake, fake, fake, None, None) == 1
+    assert lib.pf_fit_rects(plan, fake, need, fake, 3, ctypes.c_void_p(0x10001), fake, fake,
+                            None, None) == 6
+    # a workspace sized for a smaller frame is refused before anything is read
+    assert lib.pf_fit_rects(plan, fake, need - 8, fake, 3, fake, fake, fake, None, None) == 7
     lib.pf_plan_destroy(plan)
 
 
@@ -294,3 +296,49 @@ def test_default_band_height_is_whole_rounds(H, W, k, mode, rows):
     round and capped at the frame height."""
     p = pf.Plan((525.0, 525.0, W / 2 - 0.5, H / 2 - 0.5), H, W, k, mode)
     assert p.tile_h == rows
+
+
+def test_derive_leaves_the_plan_alone():
+    """pf_plan_derive makes a new plan with another band height; the source
+    plan (shared by every caller of the Python cache) is never written."""
+    lib = pf.load_library()
+    code, plan = _create(H=480, W=640, k=9)
+    assert code == 0
+    before = lib.pf_plan_band_height(plan)
+    out = ctypes.c_void_p()
+    assert lib.pf_plan_derive(plan, 12, ctypes.byref(out)) == 0
+    assert lib.pf_plan_band_height(out) == 12
+    assert lib.pf_plan_band_height(plan) == before
+    big = ctypes.c_void_p()
+    assert lib.pf_plan_derive(plan, 100000, ctypes.byref(big)) == 0
+    assert lib.pf_plan_band_height(big) == 480              # clamped to the frame
+    bad = ctypes.c_void_p(1)
+    assert lib.pf_plan_derive(plan, 0, ctypes.byref(bad)) == 2
+    assert bad.value is None
+    assert lib.pf_plan_derive(None, 8, ctypes.byref(bad)) == 1
+    for h in (out, big, plan):
+        lib.pf_plan_destroy(h)
+
+
+def test_output_tensor_checks():
+    """The binding refuses out tensors of the wrong shape, dtype, layout or
+    device before any pointer reaches the library (the kernels write the
+    plan's [3,H,W] / [H,W] shapes whatever they are given)."""
+    import torch
+    from paper_2103_06644_amd._binding import _check_outs
+    H, W, dev = 6, 8, torch.device("cpu")
+    good = (torch.empty(3, H, W), torch.empty(H, W), torch.empty(H, W),
+            torch.empty(H, W, dtype=torch.uint8))
+    _check_outs(torch, good, H, W, dev)
+    bad = [
+        (torch.empty(3, H, W + 1),) + good[1:],                       # shape
+        good[:1] + (torch.empty(H, W, dtype=torch.float64),) + good[2:],  # dtype
+        good[:2] + (torch.empty(W, H).t(),) + good[3:],               # not contiguous
+        good[:3] + (torch.empty(H, W),),                              # status dtype
+        good[:3],                                                     # missing tensor
+    ]
+    for b in bad:
+        with pytest.raises(ValueError):
+            _check_outs(torch, b, H, W, dev)
+    with pytest.raises(ValueError):
+        _check_outs(torch, good, H, W, torch.device("meta"))          # device

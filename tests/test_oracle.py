@@ -132,6 +132,14 @@ MUTATIONS = {
     "largest_eigvec": ("double n[3] = {V[0], V[3], V[6]};\n  unit_from(n, f->n);\n  f->d = -(f->n[0] * c[0]",
                        "double n[3] = {V[2], V[5], V[8]};\n  unit_from(n, f->n);\n  f->d = -(f->n[0] * c[0]"),
     "centroid_unweighted_z": ("c[2] += w * Z[i];", "c[2] += Z[i];"),
+    "kappa_l3_over_l2": ("? ev[2] / (ev[1] - ev[0]) : INFINITY;", "? ev[2] / ev[1] : INFINITY;"),
+    "tie_break_dropped": ("  else if (f->n[2] != 0.0)\n    flip = f->n[2] > 0.0;\n"
+                          "  else if (f->n[1] != 0.0)\n    flip = f->n[1] > 0.0;\n"
+                          "  else\n    flip = f->n[0] > 0.0;",
+                          "  else\n    flip = 0;"),
+    "xyz_implicit_weighted": ("case PFO_XYZ_IMPLICIT: fit_implicit_pca(X, Y, Z, N, 0, &f);",
+                              "case PFO_XYZ_IMPLICIT: fit_implicit_pca(X, Y, Z, N, 1, &f);"),
+    "xyz_explicit_dropped_y": ("double c = mz - a * mx - b * my;", "double c = mz - a * mx;"),
 }
 
 

@@ -13,7 +13,7 @@ import pytest
 import oracle
 import parity as PT
 from depthsynth import camera_for, exact_plane_depth, frames_for
-from oracle_pins import EXACT_PLANES
+from oracle_pins import EXACT_PLANES, tie_break_frame
 
 pytestmark = pytest.mark.gpu
 
@@ -198,3 +198,28 @@ def test_kappa_flag_marks_ill_conditioned(gpu):
     # the GPU's kappa estimate tracks the oracle's: decisively conditioned windows agree
     assert not flagged[v & (o["kappa"] < 1e3)].any()
     assert flagged[v & (o["kappa"] > 1e5)].all()
+
+
+@pytest.mark.parametrize("fx,fy,want", [(64.0, 32.0, (-1.0, 0.0, 0.0)), (32.0, 64.0, (0.0, -1.0, 0.0))])
+def test_orientation_tie_break(gpu, fx, fy, want):
+    """A window whose best plane passes through the camera centre (d = 0): the
+    normal's sign is settled by the tie-break (first non-zero of n_z, n_y, n_x
+    negative), as in the oracle.  The 5 x 5 symmetric pattern of depths 1/2
+    and 1 sits in a 32-pixel-wide frame of unit depth; every integrand and sum
+    is a short dyadic number, so the window's moments are exact on both sides
+    and d comes out exactly 0."""
+    import paper_2103_06644_amd as pf
+    import torch
+    pat, _ = tie_break_frame(fx, fy)
+    z = np.ones((5, 32), np.float32)
+    z[:, 13:18] = pat
+    intr = (fx, fy, 15.0, 2.0)
+    _say("tie-break", fx, fy)
+    g = PT.gpu_fit(z, intr, 5, "implicit")
+    o = oracle.fit_planes(z.astype(np.float64), intr, 5, "implicit")
+    assert o["status"][2, 15] == 0 and o["offsets"][2, 15] == 0.0
+    assert np.array_equal(o["normals"][:, 2, 15], np.array(want))
+    assert g["status"][2, 15] == 0
+    assert np.array_equal(g["normals"][:, 2, 15], np.array(want)), g["normals"][:, 2, 15]
+    assert g["offsets"][2, 15] == 0.0
+    PT.assert_parity(PT.check(g, o, "implicit", z, intr))

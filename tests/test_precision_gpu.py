@@ -7,8 +7,9 @@ bucketed by the oracle's eigen-condition kappa = l3 / (l2 - l1).  The raw 2-norm
 condition number of the uncentred 4x4 scatter matrix of Eq. 14 is reported
 beside it (it is large for clean windows, so it is not the gate).
 
-The FP64 and compensated paths are held to the parity tolerances; the FP32 path
-is reported only.  The table is printed, and also written as
+The FP64 and compensated paths are held to the parity tolerances (angle,
+offset relative to d with the 1e-3 |P_c| floor, residual within 1e-4 r + 1e-7);
+the FP32 path is reported only.  The table is printed, and also written as
 precision_report_k<k>.json into the directory named by the environment
 variable PF_REPORT_DIR when it is set.
 """
@@ -62,11 +63,17 @@ def _errors(g, o, sel, f, mode):
     gn = g["normals"][(slice(None),) + sel][:, ov]
     gn = gn / np.linalg.norm(gn, axis=0)
     ang = PT.angle(gn, o["normals"][:, ov])
-    scale = np.maximum(PT.centre_distance(f.depth, f.intrinsics, sel)[ov], np.abs(o["offsets"][ov]))
-    off = np.abs(g["offsets"][sel][ov] - o["offsets"][ov]) / scale
-    res = np.abs(g["residuals"][sel][ov] - o["residuals"][ov]) / np.maximum(o["residuals"][ov], 1e-12)
+    pc = PT.centre_distance(f.depth, f.intrinsics, sel)[ov]
+    od = np.abs(o["offsets"][ov])
+    derr = np.abs(g["offsets"][sel][ov] - o["offsets"][ov])
+    off = derr / np.maximum(od, PT.OFFSET_FLOOR * pc)      # relative to d (the gated measure)
+    off_pc = derr / np.maximum(od, pc)                      # relative to |P_c| (reported)
+    rr = o["residuals"][ov]
+    rerr = np.abs(g["residuals"][sel][ov] - rr)
+    res = rerr / np.maximum(rr, 1e-12)
+    res_bad = rerr > PT.residual_tol(rr)
     kap = o["kappa"][ov] if mode == "implicit" else np.ones(ov.sum())
-    return ang, off, res, kap, gs[ov]
+    return ang, off, off_pc, res, res_bad, kap, gs[ov]
 
 
 @pytest.mark.parametrize("k", [15, 31])
@@ -83,7 +90,7 @@ def test_precision_study_hd(gpu, k):
         for prec in ("fp32", "compensated", "fp64"):
             print("[case] precision", k, mode, prec, flush=True)
             g = PT.gpu_fit(f.depth, f.intrinsics, k, mode, precision=prec)
-            ang, off, res, kap, st = _errors(g, o, sel, f, mode)
+            ang, off, off_pc, res, res_bad, kap, st = _errors(g, o, sel, f, mode)
             row = {"mode": mode, "precision": prec, "n": int(ang.size),
                    "fp64_resolve_frac": float(np.mean((st & 4) != 0))}
             edges = [0, 1e1, 1e2, 1e3, 1e4, 1e6, np.inf] if mode == "implicit" else [0, np.inf]
@@ -96,11 +103,14 @@ def test_precision_study_hd(gpu, k):
                     "kappa": f"({lo:g}, {hi:g}]", "n": int(b.sum()),
                     "angle_p50": float(np.median(ang[b])), "angle_max": float(ang[b].max()),
                     "offset_p50": float(np.median(off[b])), "offset_max": float(off[b].max()),
+                    "offset_pc_max": float(off_pc[b].max()),
                     "residual_rel_p50": float(np.median(res[b])),
-                    "residual_rel_max": float(res[b].max())})
+                    "residual_rel_max": float(res[b].max()),
+                    "residual_out_of_tol": int(res_bad[b].sum())})
             gated = kap <= PT.KAPPA_GATE
             row["gated_angle_max"] = float(ang[gated].max())
             row["gated_offset_max"] = float(off[gated].max())
+            row["gated_residual_out_of_tol"] = int(res_bad[gated].sum())
             report["rows"].append(row)
     out_dir = os.environ.get("PF_REPORT_DIR")
     if out_dir:
@@ -112,6 +122,7 @@ def test_precision_study_hd(gpu, k):
         if row["precision"] in ("fp64", "compensated"):
             assert row["gated_angle_max"] <= PT.ANGLE_TOL, row
             assert row["gated_offset_max"] <= PT.OFFSET_TOL, row
+            assert row["gated_residual_out_of_tol"] == 0, row
 
 
 @pytest.mark.parametrize("mode", ["implicit", "explicit"])
@@ -124,3 +135,43 @@ def test_compensated_parity_vga(gpu, mode, k):
     print("compensated", mode, k, rep, "fp64 re-solve fraction",
           float(np.mean((g["status"] & 4) != 0)))
     PT.assert_parity(rep)
+
+
+@pytest.mark.parametrize("mode", ["implicit", "explicit"])
+def test_compensated_parity_plain(gpu, mode):
+    f = frames_for("plain_160x120")[0]
+    print("[case] compensated plain_160x120", mode, flush=True)
+    g = PT.gpu_fit(f.depth, f.intrinsics, 5, mode, precision="compensated")
+    o = PT.oracle_full(f.depth, f.intrinsics, 5, mode)
+    rep = PT.check(g, o, mode, f.depth, f.intrinsics)
+    print("compensated plain", mode, rep, flush=True)
+    PT.assert_parity(rep)
+
+
+@pytest.mark.parametrize("mode", ["implicit", "explicit"])
+def test_compensated_parity_batch(gpu, mode):
+    """The 64-frame mixed batch in compensated precision: every frame checked
+    against the oracle on seeded samples (and whole frames for the smallest)."""
+    import torch
+    import paper_2103_06644_amd as pf
+    frames = frames_for("batch_mixed_64")
+    print("[case] compensated batch_mixed_64", mode, flush=True)
+    depths = [torch.from_numpy(f.depth).cuda() for f in frames]
+    outs = pf.fit_planes_batch(depths, [f.intrinsics for f in frames], [f.window for f in frames],
+                               mode=mode, precision="compensated")
+    torch.cuda.synchronize()
+    rng = np.random.Generator(np.random.PCG64(31))
+    worst = dict(angle_max=0.0, offset_max=0.0)
+    for i, f in enumerate(frames):
+        H, W = f.depth.shape
+        ys, xs = rng.integers(0, H, 600), rng.integers(0, W, 600)
+        o = oracle.fit_points(f.depth.astype(np.float64), f.intrinsics, f.window, xs, ys, mode)
+        g = dict(normals=outs[i][0].cpu().numpy().astype(np.float64),
+                 offsets=outs[i][1].cpu().numpy().astype(np.float64),
+                 residuals=outs[i][2].cpu().numpy().astype(np.float64),
+                 status=outs[i][3].cpu().numpy())
+        rep = PT.check(g, o, mode, f.depth, f.intrinsics, sel=(ys, xs))
+        PT.assert_parity(rep)
+        for key in worst:
+            worst[key] = max(worst[key], rep[key])
+    print("compensated batch", mode, worst, flush=True)

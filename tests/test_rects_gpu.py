@@ -50,14 +50,15 @@ def seeded_rects(H, W, n, seed, min_side=2, max_side=200):
 
 
 def rect_scale(depth, intr, rects, offsets):
-    """max(|d|, |P| at the rectangle's centre pixel), the offset error scale."""
+    """max(|d|, 1e-3 |P| at the rectangle's centre pixel), the offset error
+    scale (relative to d, floored where the plane passes near the camera)."""
     fx, fy, cx, cy = intr
     H, W = depth.shape
     xc = np.clip(rects[:, 0] + (rects[:, 2] - 1) // 2, 0, W - 1)
     yc = np.clip(rects[:, 1] + (rects[:, 3] - 1) // 2, 0, H - 1)
     z = depth[yc, xc].astype(np.float64)
     pc = z * np.sqrt(((xc - cx) / fx) ** 2 + ((yc - cy) / fy) ** 2 + 1)
-    return np.maximum(pc, np.abs(offsets))
+    return np.maximum(PT.OFFSET_FLOOR * pc, np.abs(offsets))
 
 
 def check_rects(g, o, mode, depth, intr, rects):

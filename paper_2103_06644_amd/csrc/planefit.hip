@@ -566,6 +566,126 @@ __device__ inline void finish_implicit(const FitArgs& a, const Implicit3<S>& c, 
 }
 
 // ---------------------------------------------------------------------------
+// FP64 implicit solve (Eq. 14 with |(a, b, c)| = 1), the hot path's solve.
+//
+// G is taken scaled by sum w^2, G' = Sww G = Sww diag(S2, S2, N) - g g^T with
+// g = (Sxw, Syw, Sw), so no reciprocal is needed before the offset; eigenvectors
+// are unchanged and eigenvalues scale by Sww.  C = M^T G' M in the normal's
+// coordinates.  FP64 has the range for these sums at every supported depth
+// (1e-3 .. 1e3, k <= 63), so there is no power-of-two scaling.
+//
+// Smallest eigenvalue: Halley's iteration on det(C - l I) from the lower bound
+// c0/c1 (convex and decreasing below l1, so the iterates rise monotonically).
+// Halley's error obeys e' ~ e^3 / gap^2 with gap = l2 - l1 >= -f'(l)/(c2 - 3l),
+// so the loop stops once a step s has s (c2 - 3l) <= 1e-4 (-f'(l)): the
+// remaining error is then below 1e-12 of the gap (measured on the workload
+// frames: at most 1.5e-10 rad from the converged eigenvector, about one Halley
+// iteration fewer than stopping on a negligible step), or on a step below
+// 1e-13 c2.
+//
+// Eigenvector: the column of adj(C - l1 I) with the largest diagonal entry.
+// adj(C - l I) = sum_k prod_{j != k} (l_j - l) e_k e_k^T is positive
+// semidefinite for l <= l1 and its e_1 weight dominates, so every column is
+// parallel to e_1 at l = l1 and the largest diagonal picks a column with
+// |e_1j|^2 >= 1/3.  Each column is the cross product of two rows of C - l I
+// (the approach of J. Kopp, 2008, for symmetric 3x3 eigenvectors).
+// Accuracy of the normal ~ eps * l3 / (l2 - l1).
+// ---------------------------------------------------------------------------
+__device__ inline PixelOut solve_implicit_fp64(const FitArgs& a, const Moments<double>& m,
+                                               double uc, double vc, bool want_kappa) {
+  PixelOut o;
+  o.st = 0;
+  o.kappa = 0.0f;
+  const double S2 = a.S2, ifx = a.inv_fx, ify = a.inv_fy;
+  const double g11 = fma(S2, m.Sww, -m.Sxw * m.Sxw), g22 = fma(S2, m.Sww, -m.Syw * m.Syw);
+  const double g33 = m.V;
+  const double g12 = -m.Sxw * m.Syw, g13 = -m.Sxw * m.Sw, g23 = -m.Syw * m.Sw;
+  const double c02 = fma(ifx, g13, uc * g33), c12 = fma(ify, g23, vc * g33), c22 = g33;
+  const double c00 = fma(ifx, fma(ifx, g11, uc * g13), uc * c02);
+  const double c01 = fma(ifx, fma(ify, g12, vc * g13), uc * c12);
+  const double c11 = fma(ify, fma(ify, g22, vc * g23), vc * c12);
+  // det(C - l I) = -l^3 + c2 l^2 - c1 l + c0
+  const double m00 = c11 * c22 - c12 * c12, m11 = c00 * c22 - c02 * c02;
+  const double m22 = c00 * c11 - c01 * c01;
+  const double c2 = c00 + c11 + c22, c1 = m00 + m11 + m22;
+  const double c0 = c00 * m00 + c01 * (c02 * c12 - c01 * c22) + c02 * (c01 * c12 - c02 * c11);
+  double l = 0.0;
+  if (c0 > 0.0 && c1 > 0.0) {
+    l = c0 * rcp_nr(c1);
+    const double tol = 1e-13 * c2;
+    for (int it = 0; it < 24; ++it) {
+      const double f = fma(fma(c2 - l, l, -c1), l, c0);
+      const double fp = fma(fma(-3.0, l, 2.0 * c2), l, -c1);
+      const double fpp = fma(-6.0, l, 2.0 * c2);
+      if (!(f > 0.0) || !(fp < 0.0)) break;
+      const double den = fma(2.0 * fp, fp, -f * fpp);
+      if (!(den > 0.0)) break;
+      // the step's reciprocal needs no refinement: an error of relative size e
+      // in a step of size s leaves e s, which the next step removes
+      const double ln = l - 2.0 * f * fp * rcp_raw(den);
+      if (!(ln > l)) break;
+      const double step = ln - l;
+      l = ln;
+      if (step <= tol || step * (c2 - 3.0 * l) <= -1e-4 * fp) break;
+    }
+  }
+  const double a00 = c00 - l, a11 = c11 - l, a22 = c22 - l;
+  const double k00 = a11 * a22 - c12 * c12, k11 = a00 * a22 - c02 * c02, k22 = a00 * a11 - c01 * c01;
+  const double q01 = c02 * c12 - c01 * a22, q02 = c01 * c12 - c02 * a11;
+  const double q12 = c01 * c02 - a00 * c12;
+  double vx = k00, vy = q01, vz = q02, best = k00;
+  if (k11 > best) { vx = q01; vy = k11; vz = q12; best = k11; }
+  if (k22 > best) { vx = q02; vy = q12; vz = k22; best = k22; }
+  double nn = vx * vx + vy * vy + vz * vz;
+  bool degenerate = false;
+  if (!(best > 0.0) || !(nn > 0.0) || !isfinite(nn)) {
+    // l1 has multiplicity >= 2 (or the window is flat in every direction): any
+    // vector orthogonal to the largest row of C - l I
+    double rx = a00, ry = c01, rz = c02;
+    double rn = rx * rx + ry * ry + rz * rz;
+    const double r1n = c01 * c01 + a11 * a11 + c12 * c12;
+    if (r1n > rn) { rx = c01; ry = a11; rz = c12; rn = r1n; }
+    const double r2n = c02 * c02 + c12 * c12 + a22 * a22;
+    if (r2n > rn) { rx = c02; ry = c12; rz = a22; rn = r2n; }
+    if (rn > 0.0) {
+      if (fabs(rx) <= fabs(ry) && fabs(rx) <= fabs(rz)) { vx = 0.0; vy = rz; vz = -ry; }
+      else if (fabs(ry) <= fabs(rz)) { vx = -rz; vy = 0.0; vz = rx; }
+      else { vx = ry; vy = -rx; vz = 0.0; }
+    } else {
+      vx = 0.0; vy = 0.0; vz = 1.0;
+    }
+    nn = vx * vx + vy * vy + vz * vz;
+    degenerate = true;
+  }
+  const double inv = rsq_nr(nn);
+  double n0 = vx * inv, n1 = vy * inv, n2 = vz * inv;
+  const double iS = rcp_nr(m.Sww);
+  double d = -fma(n0 * ifx, m.Sxw, fma(n1 * ify, m.Syw, fma(n0, uc, fma(n1, vc, n2)) * m.Sw)) * iS;
+  if (facing_flip(d, n0, n1, n2)) {
+    d = -d; n0 = -n0; n1 = -n1; n2 = -n2;
+  }
+  d = d + 0.0;  // no negative zero
+  o.n0 = float(n0);
+  o.n1 = float(n1);
+  o.n2 = float(n2);
+  o.d = float(d);
+  o.res = sqrtf(float(fmax(l, 0.0) * iS * a.inv_N));
+  if (want_kappa) {
+    // the other two eigenvalues by deflating the characteristic cubic:
+    // l2 + l3 = c2 - l1, l2 l3 = c1 - l1 (l2 + l3)
+    const double t = c2 - l;
+    const double pr = c1 - l * t;
+    const double disc = t * t - 4.0 * pr;
+    const double l3 = 0.5 * (t + (disc > 0.0 ? sqrt(disc) : 0.0));
+    const double l2 = l3 > 0.0 ? pr / l3 : 0.0;
+    const double gap = l2 - l;
+    o.kappa = (degenerate || !(gap > 0.0)) ? __builtin_inff() : float(l3 / gap);
+    if (a.kappa_flag > 0.0 && !(o.kappa <= float(a.kappa_flag))) o.st |= 2;
+  }
+  return o;
+}
+
+// ---------------------------------------------------------------------------
 // The implicit fit with the constraint exactly as Sec. II-A states it,
 // |(a, b, c, d)| = 1: the eigenvector of the smallest eigenvalue of the 4x4
 // scatter of the monomials [u, v, 1, w] (Eq. 14), assembled here from the
@@ -694,6 +814,8 @@ __device__ inline PixelOut solve_moments(const FitArgs& a, const Moments<S>& m, 
     o.n2 = -cc * inv;
     o.d = inv;
     o.res = inv * sqrtf(fmaxf(float(m.SSR), 0.0f) * float(a.inv_N));
+  } else if constexpr (std::is_same<S, double>::value) {
+    return solve_implicit_fp64(a, m, uc, vc, a.kappa_flag > 0.0);
   } else {
     const Implicit3<S> c = implicit_matrix<S>(a, m, uc, vc);
     const bool flag = a.kappa_flag > 0.0;
@@ -836,11 +958,15 @@ __device__ inline PixelOut solve_pixel_df(const FitArgs& a, df32 B, df32 Sxw, df
     const double nn = n0 * n0 + n1 * n1 + n2 * n2;
     o.res = float(sqrt(fmax(rq / nn, 0.0) * c.iN));
   }
-  if (!(o.kappa <= float(a.kappa_fp64))) {
-    o.st = 4;
-    const bool flag = a.kappa_flag > 0.0;
-    finish_implicit<double, double>(a, c, smallest_eig<double>(c.c00, c.c01, c.c02, c.c11,
-                                                               c.c12, c.c22, flag), o, flag);
+  // The FP32 eigenvector's error (~ eps32 kappa) moves the offset by about
+  // |P_c| times that angle, |P_c| ~ |(u_c, v_c, 1)| N / sum w the distance of
+  // the window's centre point; re-solve in FP64 where kappa max(1, |P_c| / d)
+  // exceeds the threshold, which bounds both errors relative to d.
+  const double pc = sqrt(1.0 + uc * uc + vc * vc) * a.N / md.Sw;
+  const double amp = fmax(1.0, pc / fabs(double(o.d)));
+  if (!(double(o.kappa) * amp <= a.kappa_fp64)) {
+    o = solve_implicit_fp64(a, md, uc, vc, a.kappa_flag > 0.0);
+    o.st |= 4;
   }
   return o;
 }

@@ -222,4 +222,25 @@ def test_orientation_tie_break(gpu, fx, fy, want):
     assert g["status"][2, 15] == 0
     assert np.array_equal(g["normals"][:, 2, 15], np.array(want)), g["normals"][:, 2, 15]
     assert g["offsets"][2, 15] == 0.0
-    PT.assert_parity(PT.check(g, o, "implicit", z, intr))
+    # every window of the middle row sees a frame that is symmetric in y, so
+    # its plane passes through (or within rounding of) the camera centre; where
+    # the oracle's d is only rounding, the sign of (n, d) is not determined by
+    # the data and is compared up to sign; everything else is held to parity
+    pc = PT.centre_distance(z, intr)
+    tie = (o["status"] == 0) & (np.abs(o["offsets"]) <= 1e-9 * pc)
+    tie[2, 15] = False
+    if tie.any():
+        gn, on = g["normals"][:, tie], o["normals"][:, tie]
+        ang = PT.angle(gn / np.linalg.norm(gn, axis=0), on)
+        assert np.minimum(ang, np.pi - ang).max() <= PT.ANGLE_TOL
+        assert np.abs(g["offsets"][tie]).max() <= 1e-6 * pc[tie].max()
+    rest = dict(g)
+    rest["status"] = g["status"].copy()
+    o2 = {key: v.copy() for key, v in o.items()}
+    o2["status"][tie] = 1
+    rest["status"][tie] = 1
+    rest["normals"] = g["normals"].copy()
+    rest["normals"][:, tie] = np.nan
+    rest["offsets"] = g["offsets"].copy()
+    rest["offsets"][tie] = np.nan
+    PT.assert_parity(PT.check(rest, o2, "implicit", z, intr))

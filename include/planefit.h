@@ -216,6 +216,27 @@ typedef struct {
 pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io, int32_t n,
                               void* stream);
 
+/* Bytes of device workspace pf_fit_planes_batch_queued needs for n frames (a
+ * 256-byte queue header and one job record per frame); 0 for n <= 0. */
+size_t pf_batch_workspace_bytes(int32_t n);
+
+/* The fits of n frames (any number, sizes and window sizes) in ONE persistent
+ * kernel launch (Sec. II-C: many fits from one pass over each frame).  The grid
+ * is the chip's resident workgroups; each workgroup pulls its next work item (a
+ * band x strip tile of one frame, largest windows first) from a counter in
+ * `workspace` until all items are done.  The job table and the counter are
+ * written into `workspace` by small setup launches (one per 32 frames) whose
+ * arguments carry the table, so the call records into a HIP graph as kernel
+ * nodes only and every replay starts from a fresh queue.  Arguments, checks,
+ * plan compatibility and results are those of pf_fit_planes_batch (bit for bit
+ * the same outputs).
+ *   workspace  device, >= pf_batch_workspace_bytes(n), 256-byte aligned
+ *              (else PF_ERR_WORKSPACE); owned by the caller, rewritten by every
+ *              call: calls that overlap in time need separate workspaces. */
+pf_status pf_fit_planes_batch_queued(const pf_plan* const* plans, const pf_frame_io* io,
+                                     int32_t n, void* workspace, size_t workspace_bytes,
+                                     void* stream);
+
 /* Bytes of device workspace pf_fit_planes_backward needs: 32 * H * W (the four
  * per-window moment gradients in FP64). */
 size_t pf_backward_workspace_bytes(const pf_plan* plan);

@@ -73,6 +73,7 @@ _lib_lock = threading.Lock()
 EXPORTS = ("pf_plan_create", "pf_plan_destroy", "pf_plan_workspace_bytes", "pf_plan_autotune",
            "pf_plan_band_height", "pf_plan_derive",
            "pf_plan_camera_moments", "pf_fit_planes", "pf_fit_planes_batch",
+           "pf_batch_workspace_bytes", "pf_fit_planes_batch_queued",
            "pf_backward_workspace_bytes", "pf_fit_planes_backward",
            "pf_fit_planes_backward_batch", "pf_fit_planes_xyz",
            "pf_integral_workspace_bytes", "pf_integral_images", "pf_fit_rects",
@@ -105,6 +106,11 @@ def load_library(path: str | None = None):
         lib.pf_fit_planes.restype = i32
         lib.pf_fit_planes_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_FrameIO), i32, vp]
         lib.pf_fit_planes_batch.restype = i32
+        lib.pf_batch_workspace_bytes.argtypes = [i32]
+        lib.pf_batch_workspace_bytes.restype = ctypes.c_size_t
+        lib.pf_fit_planes_batch_queued.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_FrameIO), i32,
+                                                   vp, ctypes.c_size_t, vp]
+        lib.pf_fit_planes_batch_queued.restype = i32
         lib.pf_plan_band_height.argtypes = [vp]
         lib.pf_plan_band_height.restype = i32
         lib.pf_plan_autotune.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp,
@@ -492,9 +498,13 @@ def _mask_arg(torch, valid_mask, depth):
 
 def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="implicit",
                      precision="fp64", kappa_flag=0.0, outs=None, stream=None,
-                     disparity_scale=None, min_valid=None):
+                     disparity_scale=None, min_valid=None, queued=False, workspace=None):
     """Per-pixel plane fits of several frames (any sizes, per-frame window sizes)
-    in as few kernel launches as possible (up to 32 frames per launch).
+    in as few kernel launches as possible: up to 32 frames per launch, or with
+    queued=True all frames in one persistent launch fed by a work queue
+    (pf_fit_planes_batch_queued; `workspace` optionally a uint8 device tensor of
+    at least pf_batch_workspace_bytes(n) bytes, 256-byte aligned, else one is
+    allocated).
 
     depths       list of float32 [H_i, W_i] tensors on one HIP device
     intrinsics   one (fx, fy, cx, cy) for all frames, or a list of them
@@ -540,9 +550,25 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
     handles = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
     lib = load_library()
     with _on_device(torch, dev):
-        code = lib.pf_fit_planes_batch(handles, ios, n, _stream_handle(torch, dev, stream))
+        if queued:
+            need = int(lib.pf_batch_workspace_bytes(n))
+            if workspace is None:
+                workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+            have = workspace.numel() * workspace.element_size()
+            if workspace.device != dev or not workspace.is_contiguous() or have < need:
+                raise ValueError(f"workspace must be a contiguous device tensor of >= {need} bytes")
+            code = lib.pf_fit_planes_batch_queued(handles, ios, n,
+                                                  ctypes.c_void_p(workspace.data_ptr()), have,
+                                                  _stream_handle(torch, dev, stream))
+        else:
+            code = lib.pf_fit_planes_batch(handles, ios, n, _stream_handle(torch, dev, stream))
     _check(code)
     return results
+
+
+def batch_workspace_bytes(n: int) -> int:
+    """Bytes of device workspace a queued batch of n frames needs."""
+    return int(load_library().pf_batch_workspace_bytes(int(n)))
 
 
 def fit_planes_backward(depth, intrinsics, window: int, grad_normals=None, grad_offsets=None,

@@ -42,6 +42,8 @@
 #include <cstring>
 #include <new>
 #include <type_traits>
+#include <vector>
+#include <atomic>
 
 #include "planefit.h"
 
@@ -169,14 +171,16 @@ struct Cursor {
 };
 
 // Depth sample of (x, y), with 0 standing for "no valid sample" (outside the
-// image, masked out).  A separate load step lets the sweep issue a whole
-// group of row loads before it consumes any of them.
+// image, masked out, or `use` false).  Branch-free: the address is clamped into
+// the image so every lane loads, and the sample is selected afterwards; a group
+// of such loads can then be in flight together before any is consumed.
 template <bool MASK>
-__device__ inline float load_depth(const FitArgs& a, int x, int y) {
-  if (x < 0 || x >= a.W || y < 0 || y >= a.H) return 0.0f;
-  float z = a.depth[(int64_t)y * a.depth_pitch + x];
-  if (MASK && a.mask && a.mask[(int64_t)y * a.mask_pitch + x] == 0) z = 0.0f;
-  return z;
+__device__ inline float load_depth(const FitArgs& a, int x, int y, bool use = true) {
+  const bool in = use && x >= 0 && x < a.W && y >= 0 && y < a.H;
+  const int xc = min(max(x, 0), a.W - 1), yc = min(max(y, 0), a.H - 1);
+  float z = a.depth[(int64_t)yc * a.depth_pitch + xc];
+  if (MASK && a.mask) z = a.mask[(int64_t)yc * a.mask_pitch + xc] ? z : 0.0f;
+  return in ? z : 0.0f;
 }
 
 // Reciprocal of a positive depth: hardware estimate refined by Newton-Raphson
@@ -1104,16 +1108,20 @@ __device__ inline int64_t bwd_ws_offset(const LaunchArgs& la, int jb) {
 template <typename T, int MODE, bool BWD, bool PARTIAL>
 constexpr int kMinGroups = (MODE != PF_IMPLICIT_LITERAL && !BWD && !PARTIAL) ? 4 : 1;
 
+// Launch-wide parameters of a fit (shared by every frame of a launch).
+struct LaunchCommon {
+  double kappa_flag, kappa_fp64, dscale;
+};
+
+// One workgroup tile: strip `wg % n_strips`, band `wg / n_strips` of frame
+// `job`.  Called once per workgroup by fit_planes_fused and once per work item
+// by the persistent fit_planes_queued, which share every instruction of it.
 template <typename T, int MODE, bool MASK, bool BWD = false, bool PARTIAL = false>
-__global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD, PARTIAL>)) void fit_planes_fused(LaunchArgs la) {
+__device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCommon& lc,
+                                         double* gws) {
   static_assert(!PARTIAL || (std::is_same<T, double>::value && !BWD && MODE != PF_IMPLICIT_LITERAL),
                 "partial windows: FP64 forward, implicit or explicit");
   using TL = Tiling<MODE>;
-  // which job and which of its workgroups (the job table is uniform: scalar loop)
-  int jb = 0;
-  while (jb + 1 < la.n_jobs && int(blockIdx.x) >= la.jobs[jb + 1].wg_begin) ++jb;
-  const Job& job = la.jobs[jb];
-  const int wg = int(blockIdx.x) - job.wg_begin;
   FitArgs a;
   a.depth = job.depth;
   a.mask = job.mask;
@@ -1142,12 +1150,11 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD, PARTIAL>)) void f
   a.inv_N = 1.0 / a.N;
   a.S2 = a.N * (a.N - 1.0) / 12.0;
   a.inv_S2 = 1.0 / a.S2;
-  a.kappa_flag = la.kappa_flag;
-  a.kappa_fp64 = la.kappa_fp64;
+  a.kappa_flag = lc.kappa_flag;
+  a.kappa_fp64 = lc.kappa_fp64;
   a.vec_store = job.vec_store;
-  a.gws = nullptr;
-  if constexpr (BWD) a.gws = la.gws + bwd_ws_offset(la, jb);
-  a.dscale = la.dscale;
+  a.gws = gws;
+  a.dscale = lc.dscale;
   a.min_valid = job.min_valid;
 
   __shared__ T sw[TL::rows * kPitch];
@@ -1169,12 +1176,41 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD, PARTIAL>)) void f
   const int y_ref = yb + a.tile_h / 2;
   const bool col_used = tid < a.tile_w + a.k - 1;
 
+  // Every load of the prologue is issued before any is consumed: the reference
+  // row, up to kWarm warm-up rows and the first round's rows (the warm-up
+  // samples need the reference disparity, whose reduction would otherwise put
+  // one memory latency per group of rows on the band's critical path).
+  const int nwarm = a.k - 1;  // the column sums first take rows yb-r .. yb+r-1
+  constexpr int kWarmGroup = 8, kWarm = 16;
+  float zw[kWarm];
+  auto issue_warm = [&](int c0) {
+#pragma unroll
+    for (int g = 0; g < kWarm / kWarmGroup; ++g) {
+      if (c0 + g * kWarmGroup < nwarm) {  // uniform
+#pragma unroll
+        for (int j = 0; j < kWarmGroup; ++j) {
+          const int c = c0 + g * kWarmGroup + j;
+          zw[g * kWarmGroup + j] = load_depth<MASK>(a, x, yb - a.r + c, col_used && c < nwarm);
+        }
+      }
+    }
+  };
+  const float zref = load_depth<MASK>(a, x, min(y_ref, a.H - 1), col_used);
+  issue_warm(0);
+  // depth samples of the current round, loaded one round ahead
+  float zl[TL::rows], zg[TL::rows];
+#pragma unroll
+  for (int j = 0; j < TL::rows; ++j) {
+    const int y0 = yb + j;
+    zl[j] = load_depth<MASK>(a, x, y0 + a.r, y0 < ye && col_used);
+    zg[j] = load_depth<MASK>(a, x, y0 - a.r - 1, y0 < ye && y0 > yb && col_used);
+  }
+
   // Per-tile reference disparity: mean of valid w on the band's middle row.
   double ws = 0.0, wc = 0.0;
   {
-    const float z = col_used ? load_depth<MASK>(a, x, min(y_ref, a.H - 1)) : 0.0f;
-    if (depth_valid(z)) {
-      ws = disparity(z, a.dscale, 0.0);
+    if (depth_valid(zref)) {
+      ws = disparity(zref, a.dscale, 0.0);
       wc = 1.0;
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -1204,25 +1240,13 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD, PARTIAL>)) void f
   // image, up to rounding order, without carrying its two prefix sums)
   Cursor<T> col;
   col.clear();
-
-  // warm-up: the column sums take rows yb-r .. yb+r-1, TL::rows loads at a time
-  for (int c = 0; c < a.k - 1; c += TL::rows) {
-    float z[TL::rows];
+  for (int c0 = 0; c0 < nwarm; c0 += kWarm) {
+    if (c0 > 0) issue_warm(c0);  // windows above kWarm + 1 rows only
 #pragma unroll
-    for (int j = 0; j < TL::rows; ++j)
-      z[j] = (c + j < a.k - 1 && col_used) ? load_depth<MASK>(a, x, yb - a.r + c + j) : 0.0f;
-#pragma unroll
-    for (int j = 0; j < TL::rows; ++j)
-      if (c + j < a.k - 1) add_sample<T, PARTIAL>(z[j], yb - a.r + c + j, w_ref, y_ref, col, a.dscale);
-  }
-
-  // depth samples of the current round, loaded one round ahead
-  float zl[TL::rows], zg[TL::rows];
-#pragma unroll
-  for (int j = 0; j < TL::rows; ++j) {
-    const int y0 = yb + j;
-    zl[j] = (y0 < ye && col_used) ? load_depth<MASK>(a, x, y0 + a.r) : 0.0f;
-    zg[j] = (y0 < ye && y0 > yb && col_used) ? load_depth<MASK>(a, x, y0 - a.r - 1) : 0.0f;
+    for (int j = 0; j < kWarm; ++j) {
+      const int c = c0 + j;
+      if (c < nwarm) add_sample<T, PARTIAL>(zw[j], yb - a.r + c, w_ref, y_ref, col, a.dscale);
+    }
   }
 
   const int li = lds_index<MODE>(tid);
@@ -1257,8 +1281,8 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD, PARTIAL>)) void f
 #pragma unroll
       for (int j = 0; j < TL::rows; ++j) {
         const int y0 = yn + j;
-        zl[j] = (y0 < ye && col_used) ? load_depth<MASK>(a, x, y0 + a.r) : 0.0f;
-        zg[j] = (y0 < ye && col_used) ? load_depth<MASK>(a, x, y0 - a.r - 1) : 0.0f;
+        zl[j] = load_depth<MASK>(a, x, y0 + a.r, y0 < ye && col_used);
+        zg[j] = load_depth<MASK>(a, x, y0 - a.r - 1, y0 < ye && col_used);
       }
     }
     __syncthreads();
@@ -1448,6 +1472,95 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD, PARTIAL>)) void f
       }
     }
     __syncthreads();
+  }
+}
+
+template <typename T, int MODE, bool MASK, bool BWD = false, bool PARTIAL = false>
+__global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD, PARTIAL>)) void fit_planes_fused(LaunchArgs la) {
+  // which job and which of its workgroups (the job table is uniform: scalar loop)
+  int jb = 0;
+  while (jb + 1 < la.n_jobs && int(blockIdx.x) >= la.jobs[jb + 1].wg_begin) ++jb;
+  const LaunchCommon lc = {la.kappa_flag, la.kappa_fp64, la.dscale};
+  double* gws = nullptr;
+  if constexpr (BWD) gws = la.gws + bwd_ws_offset(la, jb);
+  fit_tile<T, MODE, MASK, BWD, PARTIAL>(la.jobs[jb], int(blockIdx.x) - la.jobs[jb].wg_begin, lc,
+                                        gws);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched launch.  A grid sized to the chip pulls work items (one
+// workgroup tile of one frame each, in the job table's dispatch order) from a
+// counter in device memory until the queue is drained, so frames of any number,
+// size and window run in one launch and no workgroup slot idles while items
+// remain.  The job table and the counter live in the caller's workspace; they
+// are written by queue_setup launches whose arguments carry the table by value,
+// so a batch records into a HIP graph as plain kernel nodes (no memset, no host
+// copy) and every replay starts from a fresh counter.
+// ---------------------------------------------------------------------------
+struct QueueHeader {
+  uint32_t next;     // next unclaimed work item
+  uint32_t n_items;  // work items of the whole batch
+  int32_t n_jobs;
+  int32_t reserved;
+};
+constexpr size_t kQueueHeaderBytes = 256;
+constexpr int kQueueSetupJobs = 32;  // jobs written per setup launch
+
+struct QueueSetupArgs {
+  QueueHeader* hdr;
+  Job* jobs;  // the table in the workspace
+  int32_t first, count, n_jobs;
+  uint32_t n_items;
+  Job chunk[kQueueSetupJobs];
+};
+static_assert(sizeof(QueueSetupArgs) <= 4096, "kernel arguments too large");
+static_assert(sizeof(Job) % 4 == 0, "the job table is copied as 4-byte words");
+
+__global__ __launch_bounds__(kBlock) void queue_setup(QueueSetupArgs qs) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(qs.chunk);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(qs.jobs + qs.first);
+  const int words = qs.count * int(sizeof(Job) / 4);
+  for (int i = int(threadIdx.x); i < words; i += kBlock) dst[i] = src[i];
+  if (qs.first == 0 && threadIdx.x == 0) {
+    qs.hdr->next = 0u;
+    qs.hdr->n_items = qs.n_items;
+    qs.hdr->n_jobs = qs.n_jobs;
+  }
+}
+
+struct QueueArgs {
+  QueueHeader* hdr;
+  const Job* jobs;
+  LaunchCommon lc;
+};
+
+// A job of the table read as uniform (scalar) values.
+__device__ inline Job load_job_uniform(const Job* p) {
+  Job j;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(p);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&j);
+#pragma unroll
+  for (int i = 0; i < int(sizeof(Job) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  return j;
+}
+
+template <typename T, int MODE, bool MASK, bool PARTIAL = false>
+__global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, false, PARTIAL>)) void fit_planes_queued(QueueArgs qa) {
+  __shared__ uint32_t s_item;
+  const uint32_t n_items = __builtin_amdgcn_readfirstlane(qa.hdr->n_items);
+  const int n_jobs = __builtin_amdgcn_readfirstlane(qa.hdr->n_jobs);
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&qa.hdr->next, 1u);
+    __syncthreads();
+    const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();  // every thread has the item before thread 0 claims the next one
+    if (item >= n_items) break;  // uniform: every wave of the group leaves together
+    int jb = 0;
+    while (jb + 1 < n_jobs &&
+           int(item) >= __builtin_amdgcn_readfirstlane(qa.jobs[jb + 1].wg_begin))
+      ++jb;
+    const Job job = load_job_uniform(qa.jobs + jb);
+    fit_tile<T, MODE, MASK, false, PARTIAL>(job, int(item) - job.wg_begin, qa.lc, nullptr);
   }
 }
 
@@ -2163,14 +2276,16 @@ pf_status pf_plan_camera_moments(const pf_plan* plan, int64_t x0, int64_t y0, do
   return PF_OK;
 }
 
-pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io, int32_t n,
-                              void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Host-side checks of every frame of a batch, before anything is enqueued.
+pf_status check_batch(const pf_plan* const* plans, const pf_frame_io* io, int32_t n) {
   if (n < 0) return PF_ERR_SHAPE;
   if (n == 0) return PF_OK;
   if (!plans || !io) return PF_ERR_NULL;
   auto misaligned = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 3u) != 0; };
-  auto aligned = [](const void* q, uintptr_t m) { return (reinterpret_cast<uintptr_t>(q) & m) == 0; };
-  // host-side checks of every frame before anything is enqueued
   for (int32_t i = 0; i < n; ++i) {
     const pf_plan* p = plans[i];
     const pf_frame_io& f = io[i];
@@ -2188,6 +2303,107 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
         p->dscale() != plans[0]->dscale() || p->partial() != plans[0]->partial())
       return PF_ERR_UNSUPPORTED;
   }
+  return PF_OK;
+}
+
+// The job of one frame (its workgroups start at wg_begin).
+Job make_job(const pf_plan* p, const pf_frame_io& f, int32_t wg_begin) {
+  auto aligned = [](const void* q, uintptr_t m) { return (reinterpret_cast<uintptr_t>(q) & m) == 0; };
+  Job jb;
+  std::memset(&jb, 0, sizeof(jb));
+  jb.depth = f.depth;
+  jb.mask = f.mask;
+  jb.normals = f.normals;
+  jb.offsets = f.offsets;
+  jb.residuals = f.residuals;
+  jb.status = f.status;
+  jb.fx = p->intr.fx;
+  jb.fy = p->intr.fy;
+  jb.cx = p->intr.cx;
+  jb.cy = p->intr.cy;
+  jb.depth_pitch = int32_t(f.depth_pitch);
+  jb.mask_pitch = f.mask ? int32_t(f.mask_pitch) : 0;
+  jb.H = int32_t(p->H);
+  jb.W = int32_t(p->W);
+  jb.k = p->k;
+  jb.tile_w = p->tile_w;
+  jb.tile_h = p->tile_h;
+  jb.n_strips = p->n_strips;
+  jb.wg_begin = wg_begin;
+  jb.min_valid = int16_t(p->partial() ? p->params.min_valid : 0);
+  jb.vec_store = (p->W % 4 == 0) && (p->tile_w % 4 == 0) && aligned(f.normals, 15) &&
+                 aligned(f.offsets, 15) && aligned(f.residuals, 15) &&
+                 (!f.status || aligned(f.status, 3));
+  return jb;
+}
+
+int32_t job_groups(const pf_plan* p) { return p->n_strips * p->n_bands; }
+
+LaunchCommon launch_common(const pf_plan* p) {
+  LaunchCommon lc;
+  lc.kappa_flag = p->params.kappa_flag;
+  lc.kappa_fp64 = p->params.kappa_fp64 > 0.0 ? p->params.kappa_fp64 : kDefaultKappaFp64;
+  lc.dscale = p->dscale();
+  return lc;
+}
+
+// Compute units of the current device (queried once per device).
+int device_cus() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
+  if (dev < 64) {
+    const int c = cache[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  if (dev < 64) cache[dev].store(cus, std::memory_order_relaxed);
+  return cus;
+}
+
+// One persistent launch of the instantiation for (T, MODE, MASK, PARTIAL):
+// grid = resident workgroups of the chip (occupancy x compute units), capped
+// at the number of work items.
+template <typename T, int MODE, bool MASK, bool PARTIAL>
+hipError_t launch_queued(const QueueArgs& qa, uint32_t n_items, hipStream_t s) {
+  const void* fn = reinterpret_cast<const void*>(&fit_planes_queued<T, MODE, MASK, PARTIAL>);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 1;
+  const uint32_t grid = std::min<uint32_t>(n_items, uint32_t(per_cu) * uint32_t(device_cus()));
+  hipLaunchKernelGGL((fit_planes_queued<T, MODE, MASK, PARTIAL>), dim3(grid), dim3(kBlock), 0, s,
+                     qa);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_queued_modes(const QueueArgs& qa, uint32_t n_items, int mode, bool mask,
+                               hipStream_t s) {
+  if (mode == PF_EXPLICIT)
+    return mask ? launch_queued<T, PF_EXPLICIT, true, false>(qa, n_items, s)
+                : launch_queued<T, PF_EXPLICIT, false, false>(qa, n_items, s);
+  if (mode == PF_IMPLICIT_LITERAL) {
+    if constexpr (std::is_same<T, double>::value)
+      return mask ? launch_queued<T, PF_IMPLICIT_LITERAL, true, false>(qa, n_items, s)
+                  : launch_queued<T, PF_IMPLICIT_LITERAL, false, false>(qa, n_items, s);
+    return hipErrorInvalidValue;
+  }
+  return mask ? launch_queued<T, PF_IMPLICIT, true, false>(qa, n_items, s)
+              : launch_queued<T, PF_IMPLICIT, false, false>(qa, n_items, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io, int32_t n,
+                              void* stream) {
+  const pf_status chk = check_batch(plans, io, n);
+  if (chk != PF_OK || n == 0) return chk;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int prec = plans[0]->params.precision;
   const bool expl = plans[0]->params.mode == PF_EXPLICIT;
@@ -2196,10 +2412,10 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
     LaunchArgs la;
     std::memset(&la, 0, sizeof(la));
     la.n_jobs = cnt;
-    la.kappa_flag = plans[first]->params.kappa_flag;
-    la.dscale = plans[first]->dscale();
-    la.kappa_fp64 = plans[first]->params.kappa_fp64 > 0.0 ? plans[first]->params.kappa_fp64
-                                                           : kDefaultKappaFp64;
+    const LaunchCommon lc = launch_common(plans[first]);
+    la.kappa_flag = lc.kappa_flag;
+    la.dscale = lc.dscale;
+    la.kappa_fp64 = lc.kappa_fp64;
     bool has_mask = false;
     int32_t wg = 0;
     // dispatch order (implicit solves): the jobs with the longest workgroups
@@ -2215,32 +2431,9 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
     for (int32_t j = 0; j < cnt; ++j) {
       const pf_plan* p = plans[order[j]];
       const pf_frame_io& f = io[order[j]];
-      Job& jb = la.jobs[j];
-      jb.depth = f.depth;
-      jb.mask = f.mask;
-      jb.normals = f.normals;
-      jb.offsets = f.offsets;
-      jb.residuals = f.residuals;
-      jb.status = f.status;
-      jb.fx = p->intr.fx;
-      jb.fy = p->intr.fy;
-      jb.cx = p->intr.cx;
-      jb.cy = p->intr.cy;
-      jb.depth_pitch = int32_t(f.depth_pitch);
-      jb.mask_pitch = f.mask ? int32_t(f.mask_pitch) : 0;
-      jb.H = int32_t(p->H);
-      jb.W = int32_t(p->W);
-      jb.k = p->k;
-      jb.tile_w = p->tile_w;
-      jb.tile_h = p->tile_h;
-      jb.n_strips = p->n_strips;
-      jb.wg_begin = wg;
-      jb.min_valid = int16_t(p->partial() ? p->params.min_valid : 0);
-      jb.vec_store = (p->W % 4 == 0) && (p->tile_w % 4 == 0) && aligned(f.normals, 15) &&
-                     aligned(f.offsets, 15) && aligned(f.residuals, 15) &&
-                     (!f.status || aligned(f.status, 3));
+      la.jobs[j] = make_job(p, f, wg);
       has_mask = has_mask || f.mask != nullptr;
-      wg += p->n_strips * p->n_bands;
+      wg += job_groups(p);
     }
     la.n_wg = wg;
     const dim3 grid(static_cast<unsigned>(wg));
@@ -2279,6 +2472,80 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
       g_last_hip_error = int(err);
       return PF_ERR_HIP;
     }
+  }
+  return PF_OK;
+}
+
+size_t pf_batch_workspace_bytes(int32_t n) {
+  if (n <= 0) return 0;
+  const size_t bytes = kQueueHeaderBytes + size_t(n) * sizeof(Job);
+  return (bytes + 255) / 256 * 256;
+}
+
+pf_status pf_fit_planes_batch_queued(const pf_plan* const* plans, const pf_frame_io* io,
+                                     int32_t n, void* workspace, size_t workspace_bytes,
+                                     void* stream) {
+  const pf_status chk = check_batch(plans, io, n);
+  if (chk != PF_OK || n == 0) return chk;
+  if (!workspace || workspace_bytes < pf_batch_workspace_bytes(n) ||
+      (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+    return PF_ERR_WORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // dispatch order: frames with the costliest work items (largest windows)
+  // first, so the queue ends on the cheapest ones; results do not depend on it
+  std::vector<int32_t> order(size_t(n), 0);
+  for (int32_t j = 0; j < n; ++j) order[size_t(j)] = j;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return plans[x]->k > plans[y]->k; });
+  std::vector<Job> jobs(static_cast<size_t>(n));
+  bool has_mask = false;
+  int64_t items = 0;
+  for (int32_t j = 0; j < n; ++j) {
+    const int32_t i = order[size_t(j)];
+    if (items + job_groups(plans[i]) > INT32_MAX) return PF_ERR_SHAPE;
+    jobs[size_t(j)] = make_job(plans[i], io[i], int32_t(items));
+    has_mask = has_mask || io[i].mask != nullptr;
+    items += job_groups(plans[i]);
+  }
+  QueueHeader* hdr = static_cast<QueueHeader*>(workspace);
+  Job* table = reinterpret_cast<Job*>(static_cast<char*>(workspace) + kQueueHeaderBytes);
+  for (int32_t first = 0; first < n; first += kQueueSetupJobs) {
+    QueueSetupArgs qs;
+    std::memset(&qs, 0, sizeof(qs));
+    qs.hdr = hdr;
+    qs.jobs = table;
+    qs.first = first;
+    qs.count = std::min<int32_t>(kQueueSetupJobs, n - first);
+    qs.n_jobs = n;
+    qs.n_items = uint32_t(items);
+    std::memcpy(qs.chunk, jobs.data() + first, size_t(qs.count) * sizeof(Job));
+    hipLaunchKernelGGL(queue_setup, dim3(1), dim3(kBlock), 0, s, qs);
+  }
+  hipError_t err = hipGetLastError();
+  if (err == hipSuccess) {
+    QueueArgs qa;
+    qa.hdr = hdr;
+    qa.jobs = table;
+    qa.lc = launch_common(plans[0]);
+    const int prec = plans[0]->params.precision;
+    const int mode = plans[0]->params.mode;
+    const uint32_t ni = uint32_t(items);
+    if (plans[0]->partial())
+      err = mode == PF_EXPLICIT
+                ? (has_mask ? launch_queued<double, PF_EXPLICIT, true, true>(qa, ni, s)
+                            : launch_queued<double, PF_EXPLICIT, false, true>(qa, ni, s))
+                : (has_mask ? launch_queued<double, PF_IMPLICIT, true, true>(qa, ni, s)
+                            : launch_queued<double, PF_IMPLICIT, false, true>(qa, ni, s));
+    else if (prec == PF_PREC_FP64)
+      err = launch_queued_modes<double>(qa, ni, mode, has_mask, s);
+    else if (prec == PF_PREC_FP32)
+      err = launch_queued_modes<float>(qa, ni, mode, has_mask, s);
+    else
+      err = launch_queued_modes<df32>(qa, ni, mode, has_mask, s);
+  }
+  if (err != hipSuccess) {
+    g_last_hip_error = int(err);
+    return PF_ERR_HIP;
   }
   return PF_OK;
 }

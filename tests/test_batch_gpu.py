@@ -79,3 +79,73 @@ def test_batch_with_masks_and_mixed_none(gpu):
                  residuals=outs[i][2].cpu().numpy().astype(np.float64),
                  status=outs[i][3].cpu().numpy())
         PT.assert_parity(PT.check(g, o, "implicit", f.depth, f.intrinsics))
+
+
+@pytest.mark.parametrize("mode,precision", [("implicit", "fp64"), ("explicit", "fp64"),
+                                            ("implicit", "compensated")])
+def test_queued_batch_matches_chunked(gpu, mode, precision):
+    """The persistent queued launch (all 64 frames of the mixed workload in one
+    fit launch) is bit-identical to the chunked launches, hence to single-frame
+    calls; oracle samples on a few frames."""
+    import torch
+    import paper_2103_06644_amd as pf
+    frames = _batch_frames(64)
+    print("[case] queued batch", mode, precision, len(frames), flush=True)
+    depths = [torch.from_numpy(f.depth).cuda() for f in frames]
+    intr = [f.intrinsics for f in frames]
+    ks = [f.window for f in frames]
+    a = pf.fit_planes_batch(depths, intr, ks, mode=mode, precision=precision)
+    b = pf.fit_planes_batch(depths, intr, ks, mode=mode, precision=precision, queued=True)
+    torch.cuda.synchronize()
+    for i in range(len(frames)):
+        for x, y in zip(a[i], b[i]):
+            assert torch.equal(torch.nan_to_num(x.float(), nan=-7.0),
+                               torch.nan_to_num(y.float(), nan=-7.0)), f"frame {i}"
+    rng = np.random.Generator(np.random.PCG64(19))
+    for i in (0, 31, 63):
+        f = frames[i]
+        H, W = f.depth.shape
+        ys, xs = rng.integers(0, H, 2000), rng.integers(0, W, 2000)
+        o = oracle.fit_points(f.depth.astype(np.float64), f.intrinsics, ks[i], xs, ys, mode)
+        g = dict(normals=b[i][0].cpu().numpy().astype(np.float64),
+                 offsets=b[i][1].cpu().numpy().astype(np.float64),
+                 residuals=b[i][2].cpu().numpy().astype(np.float64), status=b[i][3].cpu().numpy())
+        PT.assert_parity(PT.check(g, o, mode, f.depth, f.intrinsics, sel=(ys, xs)))
+
+
+def test_queued_batch_graph_replays(gpu):
+    """A queued batch captured in a HIP graph: every replay (with eager work and
+    synchronisations between replays) equals the eager result, since each replay
+    rewrites the job table and resets the queue counter with kernel nodes."""
+    import torch
+    import paper_2103_06644_amd as pf
+    frames = _batch_frames(40)
+    depths = [torch.from_numpy(f.depth).cuda() for f in frames]
+    intr = [f.intrinsics for f in frames]
+    ks = [f.window for f in frames]
+    outs = [(torch.empty((3,) + f.depth.shape, device="cuda"), torch.empty(f.depth.shape, device="cuda"),
+             torch.empty(f.depth.shape, device="cuda"),
+             torch.empty(f.depth.shape, dtype=torch.uint8, device="cuda")) for f in frames]
+    ws = torch.empty(pf.batch_workspace_bytes(len(frames)), dtype=torch.uint8, device="cuda")
+    ref = pf.fit_planes_batch(depths, intr, ks, queued=True, workspace=ws)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):   # warm-up on the capture stream
+        pf.fit_planes_batch(depths, intr, ks, outs=outs, queued=True, workspace=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pf.fit_planes_batch(depths, intr, ks, outs=outs, queued=True, workspace=ws)
+    for rep in range(4):
+        for o in outs:
+            for t in o:
+                t.fill_(7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(frames)):
+            for x, y in zip(outs[i], ref[i]):
+                assert torch.equal(torch.nan_to_num(x.float(), nan=-7.0),
+                                   torch.nan_to_num(y.float(), nan=-7.0)), f"replay {rep} frame {i}"

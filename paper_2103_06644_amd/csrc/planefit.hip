@@ -38,6 +38,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -487,10 +488,9 @@ __device__ inline Eig3<T> smallest_eig(T c00, T c01, T c02, T c11, T c12, T c22,
 // whether (n, d) must be negated.
 template <typename S>
 __device__ inline bool facing_flip(S d, S n0, S n1, S n2) {
-  if (d != S(0)) return d < S(0);
-  if (n2 != S(0)) return n2 > S(0);
-  if (n1 != S(0)) return n1 > S(0);
-  return n0 > S(0);
+  // the first non-zero of (d, -n_z, -n_y, -n_x) decides; selects, no branches
+  const S key = d != S(0) ? d : (n2 != S(0) ? -n2 : (n1 != S(0) ? -n1 : -n0));
+  return key < S(0);
 }
 
 struct PixelOut {
@@ -613,26 +613,30 @@ __device__ inline PixelOut solve_implicit_fp64(const FitArgs& a, const Moments<d
   const double m22 = c00 * c11 - c01 * c01;
   const double c2 = c00 + c11 + c22, c1 = m00 + m11 + m22;
   const double c0 = c00 * m00 + c01 * (c02 * c12 - c01 * c22) + c02 * (c01 * c12 - c02 * c11);
-  double l = 0.0;
-  if (c0 > 0.0 && c1 > 0.0) {
-    l = c0 * rcp_nr(c1);
-    const double tol = 1e-13 * c2;
-    for (int it = 0; it < 24; ++it) {
-      const double f = fma(fma(c2 - l, l, -c1), l, c0);
-      const double fp = fma(fma(-3.0, l, 2.0 * c2), l, -c1);
-      const double fpp = fma(-6.0, l, 2.0 * c2);
-      if (!(f > 0.0) || !(fp < 0.0)) break;
-      const double den = fma(2.0 * fp, fp, -f * fpp);
-      if (!(den > 0.0)) break;
-      // the step's reciprocal needs no refinement: an error of relative size e
-      // in a step of size s leaves e s, which the next step removes
-      const double ln = l - 2.0 * f * fp * rcp_raw(den);
-      if (!(ln > l)) break;
-      const double step = ln - l;
-      l = ln;
-      if (step <= tol || step * (c2 - 3.0 * l) <= -1e-4 * fp) break;
-    }
-  }
+  // One Halley step from l; `done` once a guard fails or the stopping rule
+  // holds (then l stays).  The step's reciprocal needs no refinement: an error
+  // of relative size e in a step of size s leaves e s, which the next step
+  // removes.
+  const double tol = 1e-13 * c2;
+  auto halley = [&](double& l, bool& done) {
+    const double f = fma(fma(c2 - l, l, -c1), l, c0);
+    const double fp = fma(fma(-3.0, l, 2.0 * c2), l, -c1);
+    const double fpp = fma(-6.0, l, 2.0 * c2);
+    const double den = fma(2.0 * fp, fp, -f * fpp);
+    const double ln = l - 2.0 * f * fp * rcp_raw(den);
+    const bool ok = !done && f > 0.0 && fp < 0.0 && den > 0.0 && ln > l;
+    const double step = ln - l;
+    done = !ok || step <= tol || step * (c2 - 3.0 * ln) <= -1e-4 * fp;
+    l = ok ? ln : l;
+  };
+  const bool start = c0 > 0.0 && c1 > 0.0;
+  double l = start ? c0 * rcp_nr(c1) : 0.0;
+  bool done = !start;
+  // almost every window takes two steps: straight-line code, then a loop for
+  // the rest
+  halley(l, done);
+  halley(l, done);
+  for (int it = 2; it < 24 && !done; ++it) halley(l, done);
   const double a00 = c00 - l, a11 = c11 - l, a22 = c22 - l;
   const double k00 = a11 * a22 - c12 * c12, k11 = a00 * a22 - c02 * c02, k22 = a00 * a11 - c01 * c01;
   const double q01 = c02 * c12 - c01 * a22, q02 = c01 * c12 - c02 * a11;
@@ -2374,6 +2378,9 @@ hipError_t launch_queued(const QueueArgs& qa, uint32_t n_items, hipStream_t s) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess ||
       per_cu <= 0)
     per_cu = 1;
+  if (std::getenv("PF_QUEUE_DEBUG"))
+    std::fprintf(stderr, "planefit queued launch: %d workgroups per CU x %d CUs, %u items\n",
+                 per_cu, device_cus(), n_items);
   const uint32_t grid = std::min<uint32_t>(n_items, uint32_t(per_cu) * uint32_t(device_cus()));
   hipLaunchKernelGGL((fit_planes_queued<T, MODE, MASK, PARTIAL>), dim3(grid), dim3(kBlock), 0, s,
                      qa);

@@ -127,13 +127,16 @@ def time_launches(torch, pf, rig, intr, ks, mode, precision, steps, warmup):
     t_end.record()
     torch.cuda.synchronize()
     per_launch = float(sum(a.elapsed_time(b) for a, b in evs)) / (n_rep * chunk)
+    time_launches.sets_used = min(rig.sets, n_rep * chunk, len(graphs) * chunk)
     return t_start.elapsed_time(t_end) / steps, per_launch
 
 
-def batch_measure(torch, pf, np, frames_for):
+def batch_measure(torch, pf, np, frames_for, queued=False):
     """The 64-frame mixed workload (320x240, 640x480, 1280x720; per-frame k):
-    one batched call (two launches of up to 32 frames), eager and replayed from a
-    captured HIP graph; two input/output sets alternate."""
+    one batched call, eager and replayed from a captured HIP graph; two
+    input/output sets alternate.  queued=False: two launches of up to 32 frames
+    each; queued=True: one persistent fit launch fed by a work queue (after its
+    small job-table setup launches)."""
     frames = frames_for("batch_mixed_64")
     sets = []
     for _ in range(2):
@@ -145,9 +148,12 @@ def batch_measure(torch, pf, np, frames_for):
     intr = [f.intrinsics for f in frames]
     ks = [f.window for f in frames]
     px = sum(f.depth.size for f in frames)
+    wss = [torch.empty(pf.batch_workspace_bytes(len(frames)), dtype=torch.uint8, device="cuda")
+           for _ in range(2)]
 
     def call(s):
-        pf.fit_planes_batch(sets[s][0], intr, ks, mode="implicit", outs=sets[s][1])
+        pf.fit_planes_batch(sets[s][0], intr, ks, mode="implicit", outs=sets[s][1],
+                            queued=queued, workspace=wss[s])
 
     for i in range(5):
         call(i % 2)
@@ -180,6 +186,7 @@ def batch_measure(torch, pf, np, frames_for):
     torch.cuda.synchronize()
     graph = a.elapsed_time(b) / n
     return {"frames": len(frames), "pixels": px, "mode": "implicit", "precision": "fp64",
+            "launch": "queued (one persistent fit launch)" if queued else "chunked (32 frames per launch)",
             "eager_ms": round(eager, 4), "graph_ms": round(graph, 4),
             "eager_Mpx_s": round(px / (eager * 1e-3) / 1e6, 1),
             "graph_Mpx_s": round(px / (graph * 1e-3) / 1e6, 1)}
@@ -208,8 +215,10 @@ def diff_measure(torch, pf, np, frames_for, diff_loss_inputs):
     grads = [torch.empty((H, W), device="cuda") for _ in frames]
     pf.get_plan(intr, H, W, k, "implicit", "fp64")
 
-    def fwd():
-        pf.fit_planes_batch(depth, intr, k, mode="implicit", outs=outs)
+    pf.get_plan(intr, H, W, k, "implicit", "fp32")
+
+    def fwd(prec="fp64"):
+        pf.fit_planes_batch(depth, intr, k, mode="implicit", precision=prec, outs=outs)
 
     def bwd():
         pf.fit_planes_backward_batch(depth, intr, k, [u[0] for u in ups], None,
@@ -219,9 +228,13 @@ def diff_measure(torch, pf, np, frames_for, diff_loss_inputs):
         fwd()
         bwd()
 
+    def both32():
+        fwd("fp32")
+        bwd()
+
     res = {"frames": len(frames), "pixels": len(frames) * H * W, "k": k, "mode": "implicit",
-           "precision": "fp64"}
-    for name, fn in (("fwd_bwd", both), ("bwd", bwd)):
+           "precision": "forward fp64 (fwd_bwd) or fp32 (fwd32_bwd); backward fp64"}
+    for name, fn in (("fwd_bwd", both), ("fwd32_bwd", both32), ("bwd", bwd)):
         for _ in range(3):
             fn()
         torch.cuda.synchronize()
@@ -364,6 +377,49 @@ def _time_calls(torch, run, sets, n_graph=16, reps=5):
     return a.elapsed_time(b) / (reps * n_graph)
 
 
+def latency_measure(torch, pf, frames_for):
+    """Single-frame latency of the 160x120 workload (k = 5, implicit FP64): the
+    time from enqueue to completion of one fit, eager (host call + launch +
+    synchronisation) and as one replay of a captured HIP graph; medians of 50."""
+    f = frames_for("plain_160x120")[0]
+    d = torch.from_numpy(f.depth).cuda()
+    H, W = f.depth.shape
+    out = (torch.empty((3, H, W), device="cuda"), torch.empty((H, W), device="cuda"),
+           torch.empty((H, W), device="cuda"), torch.empty((H, W), dtype=torch.uint8, device="cuda"))
+    run = lambda: pf.fit_planes(d, f.intrinsics, 5, out=out)
+    for _ in range(5):
+        run()
+    torch.cuda.synchronize()
+    eager = []
+    for _ in range(50):
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        eager.append((time.perf_counter() - t0) * 1e6)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            run()
+    torch.cuda.current_stream().wait_stream(side)
+    g.replay()
+    torch.cuda.synchronize()
+    graph, kern = [], []
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(50):
+        t0 = time.perf_counter()
+        a.record()
+        g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        graph.append((time.perf_counter() - t0) * 1e6)
+        kern.append(a.elapsed_time(b) * 1e3)
+    med = lambda v: round(sorted(v)[len(v) // 2], 1)
+    return {"frame": "plain_160x120", "k": 5, "eager_us": med(eager), "graph_us": med(graph),
+            "device_us": med(kern)}
+
+
 def autotune_measure(torch, pf, frames_for):
     """Single-frame 640x480 launches at k = 9 with the plan's built-in band
     height, then with the band height pf_plan_autotune picks (a derived plan;
@@ -386,16 +442,28 @@ def autotune_measure(torch, pf, frames_for):
     return res
 
 
-def cpu_baseline(frame, ks, mode, budget_s):
+def cpu_model():
+    """The host CPU's model string (lscpu / /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(frame, ks, mode, budget_s, threads=None):
     """The FP64 oracle on the host: random sample of window centres, growing until
     about budget_s seconds of work; returns Mpixel/s and what was sampled."""
     import numpy as np
     import oracle
     z = frame.depth.astype(np.float64)
     H, W = z.shape
-    threads = os.cpu_count() or 1
-    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
-        threads = max(1, min(threads, int(os.environ["OMP_NUM_THREADS"])))
+    if threads is None:
+        threads = os.cpu_count() or 1
+        if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+            threads = max(1, min(threads, int(os.environ["OMP_NUM_THREADS"])))
     rng = np.random.Generator(np.random.PCG64(7))
     n = 2000
     total_px, total_t = 0, 0.0
@@ -413,6 +481,7 @@ def cpu_baseline(frame, ks, mode, budget_s):
         n = int(n * min(8.0, max(1.5, (budget_s - total_t) / max(dt, 1e-3))))
         n = min(n, 5_000_000)
     return dict(value=total_px / total_t / 1e6, unit="Mpixel/s", cores=threads, kind="oracle",
+                cpu=cpu_model(),
                 sample=f"{total_px} random window centres of the 640x480 frame, "
                        f"k in {list(ks)}, {mode} mode, FP64, {total_t:.1f} s")
 
@@ -430,12 +499,26 @@ def main():
     from depthsynth import diff_loss_inputs, frames_for
 
     pf.load_library()
-    if args.copy_probe:
+    copy_probe = None
+    if args.copy_probe or not args.no_extras:
+        # achievable HBM bandwidth: a 256 MiB device-to-device copy (read + write)
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(10):
+            dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 10
+        nbytes = 2 * src.numel() * 4
+        copy_probe = {"bytes_moved": nbytes, "ms": round(ms, 4),
+                      "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                      "frac_of_peak": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         del src, dst
+        torch.cuda.empty_cache()
     f = frames_for("vga_640x480")[0]
     ks = (3, 5, 9, 15)
     rig = Rig(torch, f.depth, args.sets, per_set=len(ks))
@@ -454,7 +537,7 @@ def main():
                                "spheres, 0.5-6 m, Kinect noise, 10% holes), windows k=3,5,9,15, "
                                "implicit fit, FP64 moments", "frame": [480, 640],
                    "windows": list(ks), "mode": "implicit", "precision": "fp64",
-                   "buffer_sets": args.sets},
+                   "buffer_sets": time_launches.sets_used},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(),
@@ -464,7 +547,15 @@ def main():
                      "avg_launch_ms": round(avg_launch_ms, 5)},
     }
     if not args.no_extras:
-        extras = {}
+        extras = {"copy_probe_256MiB": copy_probe}
+        # per-window throughput of single-frame launches at 640x480: the
+        # integral-image fit's cost per pixel should not grow with the window
+        per_k = {}
+        for mode in ("implicit", "explicit"):
+            for k in ks:
+                ms, avg = time_launches(torch, pf, rig, f.intrinsics, (k,), mode, "fp64", 64, 5)
+                per_k[f"{mode}_k{k}"] = round(rig.pixels / (ms * 1e-3) / 1e6, 1)
+        extras["vga_single_frame_per_k_Mpx_s"] = per_k
         for mode, prec in (("explicit", "fp64"), ("implicit", "fp32"), ("explicit", "fp32"),
                            ("implicit", "compensated"), ("explicit", "compensated")):
             ms, _ = time_launches(torch, pf, rig, f.intrinsics, ks, mode, prec, 64, 5)
@@ -507,6 +598,8 @@ def main():
         del rig_hd
         torch.cuda.empty_cache()
         extras["batch_mixed_64"] = batch_measure(torch, pf, np, frames_for)
+        extras["batch_mixed_64_queued"] = batch_measure(torch, pf, np, frames_for, queued=True)
+        extras["latency_160x120"] = latency_measure(torch, pf, frames_for)
         extras["diff_8x640x480"] = diff_measure(torch, pf, np, frames_for, diff_loss_inputs)
         extras["xyz_vs_rgbd"] = xyz_measure(torch, pf, frames_for)
         extras["rects_1080p"] = rects_measure(torch, pf, np, frames_for)
@@ -514,6 +607,8 @@ def main():
         out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(f, ks, "implicit", args.cpu_seconds)
+        one = cpu_baseline(f, ks, "implicit", max(2.0, args.cpu_seconds / 4), threads=1)
+        out["cpu_baseline"]["one_thread"] = {"value": one["value"], "sample": one["sample"]}
     print(json.dumps(out), flush=True)
 
 

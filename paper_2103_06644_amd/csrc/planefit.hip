@@ -1548,23 +1548,40 @@ __device__ inline Job load_job_uniform(const Job* p) {
   return j;
 }
 
+// The job of work item `item`: a forward scan from the job of the workgroup's
+// previous item (items only grow), over the jobs' first items held in LDS for
+// up to kQueueLdsJobs jobs, else read from the table.
+constexpr int kQueueLdsJobs = 256;
+
 template <typename T, int MODE, bool MASK, bool PARTIAL = false>
 __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, false, PARTIAL>)) void fit_planes_queued(QueueArgs qa) {
   __shared__ uint32_t s_item;
+  __shared__ int32_t s_begin[kQueueLdsJobs];
   const uint32_t n_items = __builtin_amdgcn_readfirstlane(qa.hdr->n_items);
   const int n_jobs = __builtin_amdgcn_readfirstlane(qa.hdr->n_jobs);
-  for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&qa.hdr->next, 1u);
-    __syncthreads();
-    const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
-    __syncthreads();  // every thread has the item before thread 0 claims the next one
-    if (item >= n_items) break;  // uniform: every wave of the group leaves together
-    int jb = 0;
+  const bool lds_table = n_jobs <= kQueueLdsJobs;
+  if (lds_table)
+    for (int j = int(threadIdx.x); j < n_jobs; j += kBlock) s_begin[j] = qa.jobs[j].wg_begin;
+  if (threadIdx.x == 0) s_item = atomicAdd(&qa.hdr->next, 1u);
+  __syncthreads();
+  uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
+  __syncthreads();
+  int jb = 0;
+  while (item < n_items) {  // uniform: every wave of the group leaves together
+    // claim the next item now: the atomic's latency overlaps this item's loads
+    uint32_t next = 0;
+    if (threadIdx.x == 0) next = atomicAdd(&qa.hdr->next, 1u);
     while (jb + 1 < n_jobs &&
-           int(item) >= __builtin_amdgcn_readfirstlane(qa.jobs[jb + 1].wg_begin))
+           int(item) >= (lds_table ? s_begin[jb + 1]
+                                   : __builtin_amdgcn_readfirstlane(qa.jobs[jb + 1].wg_begin)))
       ++jb;
+    jb = __builtin_amdgcn_readfirstlane(jb);
     const Job job = load_job_uniform(qa.jobs + jb);
     fit_tile<T, MODE, MASK, false, PARTIAL>(job, int(item) - job.wg_begin, qa.lc, nullptr);
+    if (threadIdx.x == 0) s_item = next;
+    __syncthreads();
+    item = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();  // every wave has the item before thread 0 writes the next one
   }
 }
 
@@ -2403,6 +2420,69 @@ hipError_t launch_queued_modes(const QueueArgs& qa, uint32_t n_items, int mode, 
               : launch_queued<T, PF_IMPLICIT, false, false>(qa, n_items, s);
 }
 
+// The queued batch after the argument checks: dispatch order (frames with the
+// costliest work items, the largest windows, first, so the queue ends on the
+// cheapest ones; results do not depend on it), job table into `ws` by setup
+// launches, then one persistent fit launch.  `jobs` and `order` are host
+// buffers of n entries.
+pf_status enqueue_queued(const pf_plan* const* plans, const pf_frame_io* io, int32_t n, void* ws,
+                         void* stream, Job* jobs, int32_t* order) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int32_t j = 0; j < n; ++j) order[j] = j;
+  std::stable_sort(order, order + n,
+                   [&](int32_t x, int32_t y) { return plans[x]->k > plans[y]->k; });
+  bool has_mask = false;
+  int64_t items = 0;
+  for (int32_t j = 0; j < n; ++j) {
+    const int32_t i = order[j];
+    if (items + job_groups(plans[i]) > INT32_MAX) return PF_ERR_SHAPE;
+    jobs[j] = make_job(plans[i], io[i], int32_t(items));
+    has_mask = has_mask || io[i].mask != nullptr;
+    items += job_groups(plans[i]);
+  }
+  QueueHeader* hdr = static_cast<QueueHeader*>(ws);
+  Job* table = reinterpret_cast<Job*>(static_cast<char*>(ws) + kQueueHeaderBytes);
+  for (int32_t first = 0; first < n; first += kQueueSetupJobs) {
+    QueueSetupArgs qs;
+    std::memset(&qs, 0, sizeof(qs));
+    qs.hdr = hdr;
+    qs.jobs = table;
+    qs.first = first;
+    qs.count = std::min<int32_t>(kQueueSetupJobs, n - first);
+    qs.n_jobs = n;
+    qs.n_items = uint32_t(items);
+    std::memcpy(qs.chunk, jobs + first, size_t(qs.count) * sizeof(Job));
+    hipLaunchKernelGGL(queue_setup, dim3(1), dim3(kBlock), 0, s, qs);
+  }
+  hipError_t err = hipGetLastError();
+  if (err == hipSuccess) {
+    QueueArgs qa;
+    qa.hdr = hdr;
+    qa.jobs = table;
+    qa.lc = launch_common(plans[0]);
+    const int prec = plans[0]->params.precision;
+    const int mode = plans[0]->params.mode;
+    const uint32_t ni = uint32_t(items);
+    if (plans[0]->partial())
+      err = mode == PF_EXPLICIT
+                ? (has_mask ? launch_queued<double, PF_EXPLICIT, true, true>(qa, ni, s)
+                            : launch_queued<double, PF_EXPLICIT, false, true>(qa, ni, s))
+                : (has_mask ? launch_queued<double, PF_IMPLICIT, true, true>(qa, ni, s)
+                            : launch_queued<double, PF_IMPLICIT, false, true>(qa, ni, s));
+    else if (prec == PF_PREC_FP64)
+      err = launch_queued_modes<double>(qa, ni, mode, has_mask, s);
+    else if (prec == PF_PREC_FP32)
+      err = launch_queued_modes<float>(qa, ni, mode, has_mask, s);
+    else
+      err = launch_queued_modes<df32>(qa, ni, mode, has_mask, s);
+  }
+  if (err != hipSuccess) {
+    g_last_hip_error = int(err);
+    return PF_ERR_HIP;
+  }
+  return PF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2497,64 +2577,9 @@ pf_status pf_fit_planes_batch_queued(const pf_plan* const* plans, const pf_frame
   if (!workspace || workspace_bytes < pf_batch_workspace_bytes(n) ||
       (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
     return PF_ERR_WORKSPACE;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  // dispatch order: frames with the costliest work items (largest windows)
-  // first, so the queue ends on the cheapest ones; results do not depend on it
-  std::vector<int32_t> order(size_t(n), 0);
-  for (int32_t j = 0; j < n; ++j) order[size_t(j)] = j;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t x, int32_t y) { return plans[x]->k > plans[y]->k; });
   std::vector<Job> jobs(static_cast<size_t>(n));
-  bool has_mask = false;
-  int64_t items = 0;
-  for (int32_t j = 0; j < n; ++j) {
-    const int32_t i = order[size_t(j)];
-    if (items + job_groups(plans[i]) > INT32_MAX) return PF_ERR_SHAPE;
-    jobs[size_t(j)] = make_job(plans[i], io[i], int32_t(items));
-    has_mask = has_mask || io[i].mask != nullptr;
-    items += job_groups(plans[i]);
-  }
-  QueueHeader* hdr = static_cast<QueueHeader*>(workspace);
-  Job* table = reinterpret_cast<Job*>(static_cast<char*>(workspace) + kQueueHeaderBytes);
-  for (int32_t first = 0; first < n; first += kQueueSetupJobs) {
-    QueueSetupArgs qs;
-    std::memset(&qs, 0, sizeof(qs));
-    qs.hdr = hdr;
-    qs.jobs = table;
-    qs.first = first;
-    qs.count = std::min<int32_t>(kQueueSetupJobs, n - first);
-    qs.n_jobs = n;
-    qs.n_items = uint32_t(items);
-    std::memcpy(qs.chunk, jobs.data() + first, size_t(qs.count) * sizeof(Job));
-    hipLaunchKernelGGL(queue_setup, dim3(1), dim3(kBlock), 0, s, qs);
-  }
-  hipError_t err = hipGetLastError();
-  if (err == hipSuccess) {
-    QueueArgs qa;
-    qa.hdr = hdr;
-    qa.jobs = table;
-    qa.lc = launch_common(plans[0]);
-    const int prec = plans[0]->params.precision;
-    const int mode = plans[0]->params.mode;
-    const uint32_t ni = uint32_t(items);
-    if (plans[0]->partial())
-      err = mode == PF_EXPLICIT
-                ? (has_mask ? launch_queued<double, PF_EXPLICIT, true, true>(qa, ni, s)
-                            : launch_queued<double, PF_EXPLICIT, false, true>(qa, ni, s))
-                : (has_mask ? launch_queued<double, PF_IMPLICIT, true, true>(qa, ni, s)
-                            : launch_queued<double, PF_IMPLICIT, false, true>(qa, ni, s));
-    else if (prec == PF_PREC_FP64)
-      err = launch_queued_modes<double>(qa, ni, mode, has_mask, s);
-    else if (prec == PF_PREC_FP32)
-      err = launch_queued_modes<float>(qa, ni, mode, has_mask, s);
-    else
-      err = launch_queued_modes<df32>(qa, ni, mode, has_mask, s);
-  }
-  if (err != hipSuccess) {
-    g_last_hip_error = int(err);
-    return PF_ERR_HIP;
-  }
-  return PF_OK;
+  std::vector<int32_t> order(static_cast<size_t>(n), 0);
+  return enqueue_queued(plans, io, n, workspace, stream, jobs.data(), order.data());
 }
 
 pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_pitch,

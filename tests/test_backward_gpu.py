@@ -263,3 +263,42 @@ def test_backward_batch_matches_single_calls(gpu, mode):
         torch.cuda.synchronize()
         a, b = batch[i].cpu().numpy(), single.cpu().numpy()
         assert np.array_equal(a, b, equal_nan=True), (i, specs[i])
+
+
+@pytest.mark.parametrize("mode", ["implicit", "explicit"])
+def test_backward_fd_1e4_on_32x24(gpu, mode):
+    """The differentiation workload's own check on the GPU adjoint: central
+    differences of the C oracle with a 1e-4 m step (FP64) at every pixel of a
+    32 x 24 crop, k = 9, for L = sum W (1 - n . t) + 0.1 r.  Bar: the central
+    difference's truncation error (Richardson estimate against a 5e-5 m step)
+    plus GRAD_RTOL of the largest derivative; the extrapolated difference within
+    1e-5."""
+    from test_oracle_grad import c5_upstream
+    k = 9
+    z, intr = crop(_frames()[0], 300, 200, 32, 24)
+    z = z.astype(np.float32).astype(np.float64)
+    o = oracle.fit_planes(z, intr, k, mode)
+    if mode == "explicit":
+        o.pop("kappa")
+    gn, gd, gr, keep = c5_upstream(o, z, intr, 6000)
+    gn, gd, gr = f32_up(gn, gd, gr)
+    print("[case] backward fd 1e-4 32x24", mode, flush=True)
+    g = gpu_backward(z, intr, k, mode, gn, gd, gr)
+
+    def fd(h):
+        out = np.zeros_like(z)
+        for (y, x), zz in np.ndenumerate(z):
+            zp, zm = z.copy(), z.copy()
+            zp[y, x] += h
+            zm[y, x] -= h
+            out[y, x] = (loss_oracle(zp, intr, k, mode, gn, gd, gr)
+                         - loss_oracle(zm, intr, k, mode, gn, gd, gr)) / (2 * h)
+        return out
+
+    f1, f2 = fd(1e-4), fd(5e-5)
+    trunc = np.abs(f1 - f2) * 4.0 / 3.0
+    scale = np.abs(f1).max()
+    err = np.abs(g - f1)
+    print(mode, "max |gpu - fd(1e-4)| / max |fd| =", err.max() / scale, flush=True)
+    assert np.all(err <= 1.5 * trunc + GRAD_RTOL * scale)
+    assert np.abs(g - (4 * f2 - f1) / 3).max() <= 1e-5 * scale

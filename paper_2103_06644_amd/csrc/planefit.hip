@@ -1559,18 +1559,23 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, false, PARTIAL>)) void
   __shared__ int32_t s_begin[kQueueLdsJobs];
   const uint32_t n_items = __builtin_amdgcn_readfirstlane(qa.hdr->n_items);
   const int n_jobs = __builtin_amdgcn_readfirstlane(qa.hdr->n_jobs);
+  const uint32_t grid = gridDim.x;
   const bool lds_table = n_jobs <= kQueueLdsJobs;
   if (lds_table)
     for (int j = int(threadIdx.x); j < n_jobs; j += kBlock) s_begin[j] = qa.jobs[j].wg_begin;
-  if (threadIdx.x == 0) s_item = atomicAdd(&qa.hdr->next, 1u);
   __syncthreads();
-  uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
-  __syncthreads();
+  // the first item of every workgroup is its own index; later ones come from
+  // the counter, offset by the grid size
+  uint32_t item = blockIdx.x;
   int jb = 0;
   while (item < n_items) {  // uniform: every wave of the group leaves together
-    // claim the next item now: the atomic's latency overlaps this item's loads
+    // While more than two items per workgroup remain, the next item is claimed
+    // before this one runs (the atomic's latency overlaps this item's loads);
+    // near the end of the queue it is claimed only once this item is done, so
+    // the last items go to the workgroups that are free first.
+    const bool ahead = item + 2 * grid < n_items;
     uint32_t next = 0;
-    if (threadIdx.x == 0) next = atomicAdd(&qa.hdr->next, 1u);
+    if (ahead && threadIdx.x == 0) next = grid + atomicAdd(&qa.hdr->next, 1u);
     while (jb + 1 < n_jobs &&
            int(item) >= (lds_table ? s_begin[jb + 1]
                                    : __builtin_amdgcn_readfirstlane(qa.jobs[jb + 1].wg_begin)))
@@ -1578,6 +1583,7 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, false, PARTIAL>)) void
     jb = __builtin_amdgcn_readfirstlane(jb);
     const Job job = load_job_uniform(qa.jobs + jb);
     fit_tile<T, MODE, MASK, false, PARTIAL>(job, int(item) - job.wg_begin, qa.lc, nullptr);
+    if (!ahead && threadIdx.x == 0) next = grid + atomicAdd(&qa.hdr->next, 1u);
     if (threadIdx.x == 0) s_item = next;
     __syncthreads();
     item = __builtin_amdgcn_readfirstlane(s_item);
@@ -2427,6 +2433,10 @@ hipError_t launch_queued_modes(const QueueArgs& qa, uint32_t n_items, int mode, 
 // buffers of n entries.
 pf_status enqueue_queued(const pf_plan* const* plans, const pf_frame_io* io, int32_t n, void* ws,
                          void* stream, Job* jobs, int32_t* order) {
+  // up to kMaxJobs frames fit in one launch's arguments: that launch, whose
+  // workgroups the hardware dispatches, is already the single launch the
+  // queue would give, without the queue's per-item claim and table reads
+  if (n <= kMaxJobs) return pf_fit_planes_batch(plans, io, n, stream);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   for (int32_t j = 0; j < n; ++j) order[j] = j;
   std::stable_sort(order, order + n,

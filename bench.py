@@ -421,9 +421,9 @@ def latency_measure(torch, pf, frames_for):
 
 
 def autotune_measure(torch, pf, frames_for):
-    """Single-frame 640x480 launches at k = 9 with the plan's built-in band
-    height, then with the band height pf_plan_autotune picks (a derived plan;
-    the shared one is not changed)."""
+    """Single-frame 640x480 launches at k = 9 with the plan's built-in launch
+    shape, then with the band height and shape pf_plan_autotune picks (a derived
+    plan; the shared one is not changed)."""
     f = frames_for("vga_640x480")[0]
     rig = Rig(torch, f.depth, 32)
     res = {}
@@ -433,12 +433,14 @@ def autotune_measure(torch, pf, frames_for):
         run = lambda s, mode=mode: pf.fit_planes(rig.depth[s], f.intrinsics, 9, mode=mode,
                                                  out=rig.outs[s][0])
         t0 = _time_calls(torch, run, rig.sets)
-        chosen = plan.autotune(rig.depth[0])
-        run = lambda s, mode=mode, bh=chosen: pf.fit_planes(
-            rig.depth[s], f.intrinsics, 9, mode=mode, out=rig.outs[s][0], band_height=bh)
+        chosen, shape = plan.autotune(rig.depth[0])
+        run = lambda s, mode=mode, bh=chosen, sh=shape: pf.fit_planes(
+            rig.depth[s], f.intrinsics, 9, mode=mode, out=rig.outs[s][0], band_height=bh, shape=sh)
         t1 = _time_calls(torch, run, rig.sets)
-        res[mode] = {"default_band_rows": before, "default_Mpx_s": round(rig.pixels / (t0 * 1e-3) / 1e6, 1),
-                     "tuned_band_rows": chosen, "tuned_Mpx_s": round(rig.pixels / (t1 * 1e-3) / 1e6, 1)}
+        res[mode] = {"default_band_rows": before, "default_shape": plan.shape,
+                     "default_Mpx_s": round(rig.pixels / (t0 * 1e-3) / 1e6, 1),
+                     "tuned_band_rows": chosen, "tuned_shape": shape,
+                     "tuned_Mpx_s": round(rig.pixels / (t1 * 1e-3) / 1e6, 1)}
     return res
 
 

@@ -170,27 +170,40 @@ pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_p
 /* Output rows per workgroup of the plan's launches (its band height); 0 for NULL. */
 int32_t pf_plan_band_height(const pf_plan* plan);
 
-/* A new plan equal to `plan` except that its launches use `band_height` output
- * rows per workgroup (clamped to H).  `plan` is not modified; the new plan is
- * destroyed with pf_plan_destroy.  The band height changes the launch geometry
- * and which pixels share a reference disparity, so results stay within the
- * accuracy of the path but need not be bit-identical to `plan`'s.
- * PF_ERR_NULL for NULL arguments, PF_ERR_SHAPE for band_height < 1. */
-pf_status pf_plan_derive(const pf_plan* plan, int32_t band_height, pf_plan** out);
+/* Launch shapes (tiling of the fused kernel): 0 = rounds of 4 rows and runs of
+ * 4 outputs per thread at four workgroups per compute unit; 1 = the same
+ * tiling at two workgroups per compute unit (twice the registers); 2 = rounds
+ * of 8 rows and runs of 8 outputs per thread at two workgroups per compute
+ * unit.  Shapes 1 and 2 apply to PF_PREC_FP64 implicit and explicit
+ * full-window plans; every other plan runs shape 0.  Results do not depend on
+ * the shape beyond the accuracy of the path (the band height moves which pixels
+ * share a reference disparity). */
+int32_t pf_plan_shape(const pf_plan* plan);  /* -1 for NULL */
+
+/* A new plan equal to `plan` except for its launch shape: `band_height` output
+ * rows per workgroup (clamped to H; 0 = the plan's rule for that shape) and
+ * launch shape `shape` (-1 = keep).  `plan` is not modified; the new plan is
+ * destroyed with pf_plan_destroy.  PF_ERR_NULL for NULL arguments,
+ * PF_ERR_SHAPE for band_height < 0, PF_ERR_UNSUPPORTED for a shape the plan's
+ * mode and precision do not offer. */
+pf_status pf_plan_derive(const pf_plan* plan, int32_t band_height, int32_t shape,
+                         pf_plan** out);
 
 /* Autotuning of the launch shape (beside the plan's built-in heuristic): times
  * pf_fit_planes on the caller's frame and buffers with a private copy of the
- * plan for each candidate band height (output rows per workgroup: 4, 6, 8,
- * 12, 16, 24, 32, 48, 64, up to H) and returns the fastest in *chosen; apply
- * it with pf_plan_derive.  `plan` itself is never modified, so it stays safe
- * to share between threads and streams.  Arguments as pf_fit_planes; the
- * outputs are overwritten with a valid fit of the frame.  Blocks the calling
- * thread until `stream` has run the timing launches (not for use under stream
- * capture).  *chosen (optional) is written only on success. */
+ * plan for each candidate launch shape (0, 1, 2 where the plan offers them)
+ * and band height (output rows per workgroup: 4, 6, 8, 12, 16, 20, 24, 32,
+ * 48, 64, up to H, whole rounds of the shape's rows), and returns the fastest
+ * in *chosen_band_height and *chosen_shape (each optional, written only on
+ * success); apply them with pf_plan_derive.  `plan` itself is never modified,
+ * so it stays safe to share between threads and streams.  Arguments as
+ * pf_fit_planes; the outputs are overwritten with a valid fit of the frame.
+ * Blocks the calling thread until `stream` has run the timing launches (not
+ * for use under stream capture). */
 pf_status pf_plan_autotune(const pf_plan* plan, const float* depth, int64_t depth_pitch,
                            const uint8_t* mask, int64_t mask_pitch, float* normals,
                            float* offsets, float* residuals, uint8_t* status, void* stream,
-                           int32_t* chosen);
+                           int32_t* chosen_band_height, int32_t* chosen_shape);
 
 /* Device buffers of one frame for pf_fit_planes_batch (same meaning, layout and
  * ownership as the arguments of pf_fit_planes). */
@@ -208,9 +221,9 @@ typedef struct {
 /* Enqueue the fits of n frames (Sec. II-C: many fits from one pass over each
  * frame) in as few launches as possible: up to 32 frames per kernel launch,
  * of any sizes and window sizes, each described by its own plan.  All plans
- * must share mode, precision, kappa_flag, kappa_fp64 and the disparity setting,
- * and be all partial-window plans or all full-window ones (else
- * PF_ERR_UNSUPPORTED); partial-window plans may differ in min_valid.  Every
+ * must share mode, precision, kappa_flag, kappa_fp64, the disparity setting and
+ * the launch shape, and be all partial-window plans or all full-window ones
+ * (else PF_ERR_UNSUPPORTED); partial-window plans may differ in min_valid.  Every
  * frame is checked on the host as in pf_fit_planes before anything is
  * enqueued; n = 0 is a no-op.  No workspace is needed. */
 pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io, int32_t n,

@@ -71,7 +71,7 @@ _lib = None
 _lib_lock = threading.Lock()
 
 EXPORTS = ("pf_plan_create", "pf_plan_destroy", "pf_plan_workspace_bytes", "pf_plan_autotune",
-           "pf_plan_band_height", "pf_plan_derive",
+           "pf_plan_band_height", "pf_plan_derive", "pf_plan_shape",
            "pf_plan_camera_moments", "pf_fit_planes", "pf_fit_planes_batch",
            "pf_batch_workspace_bytes", "pf_fit_planes_batch_queued",
            "pf_backward_workspace_bytes", "pf_fit_planes_backward",
@@ -114,10 +114,12 @@ def load_library(path: str | None = None):
         lib.pf_plan_band_height.argtypes = [vp]
         lib.pf_plan_band_height.restype = i32
         lib.pf_plan_autotune.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp,
-                                         ctypes.POINTER(i32)]
+                                         ctypes.POINTER(i32), ctypes.POINTER(i32)]
         lib.pf_plan_autotune.restype = i32
-        lib.pf_plan_derive.argtypes = [vp, i32, ctypes.POINTER(vp)]
+        lib.pf_plan_derive.argtypes = [vp, i32, i32, ctypes.POINTER(vp)]
         lib.pf_plan_derive.restype = i32
+        lib.pf_plan_shape.argtypes = [vp]
+        lib.pf_plan_shape.restype = i32
         lib.pf_backward_workspace_bytes.argtypes = [vp]
         lib.pf_backward_workspace_bytes.restype = ctypes.c_size_t
         lib.pf_fit_planes_backward.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp,
@@ -196,11 +198,12 @@ class Plan:
     def backward_workspace_bytes(self) -> int:
         return int(self._lib.pf_backward_workspace_bytes(self._h))
 
-    def derive(self, band_height: int) -> "Plan":
-        """A new plan equal to this one except for its band height
-        (pf_plan_derive); this plan is not changed."""
+    def derive(self, band_height: int = 0, shape: int = -1) -> "Plan":
+        """A new plan equal to this one except for its launch shape: band height
+        (0 = the rule for the shape) and shape (-1 = keep) (pf_plan_derive);
+        this plan is not changed."""
         h = ctypes.c_void_p()
-        _check(self._lib.pf_plan_derive(self._h, int(band_height), ctypes.byref(h)))
+        _check(self._lib.pf_plan_derive(self._h, int(band_height), int(shape), ctypes.byref(h)))
         p = Plan.__new__(Plan)
         p._intr, p._params, p._h, p._lib = self._intr, self._params, h, self._lib
         p.intrinsics, p.height, p.width, p.window = (self.intrinsics, self.height, self.width,
@@ -208,12 +211,12 @@ class Plan:
         p.mode, p.precision, p.kappa_flag = self.mode, self.precision, self.kappa_flag
         return p
 
-    def autotune(self, depth, valid_mask=None, stream=None) -> int:
+    def autotune(self, depth, valid_mask=None, stream=None):
         """Time this plan's launch on `depth` (float32 [H, W] on the GPU) for
-        several band heights (pf_plan_autotune) and return the fastest.  The
-        plan itself is not changed: apply the result with derive() or the
-        band_height argument of fit_planes.  Blocks until the timing launches
-        have run."""
+        every launch shape and band height it offers (pf_plan_autotune) and
+        return the fastest as (band_height, shape).  The plan itself is not
+        changed: apply the result with derive() or the band_height / shape
+        arguments of fit_planes.  Blocks until the timing launches have run."""
         import torch
         _check_depth(torch, depth)
         if tuple(depth.shape) != (self.height, self.width):
@@ -225,15 +228,20 @@ class Plan:
                 torch.empty((H, W), dtype=torch.float32, device=dev),
                 torch.empty((H, W), dtype=torch.float32, device=dev),
                 torch.empty((H, W), dtype=torch.uint8, device=dev))
-        chosen = ctypes.c_int32(0)
+        chosen, shape = ctypes.c_int32(0), ctypes.c_int32(0)
         with _on_device(torch, dev):
             code = self._lib.pf_plan_autotune(
                 self._h, ctypes.c_void_p(depth.data_ptr()), depth.stride(0),
                 ctypes.c_void_p(mptr) if mptr else None, mpitch,
                 *[ctypes.c_void_p(t.data_ptr()) for t in outs],
-                _stream_handle(torch, dev, stream), ctypes.byref(chosen))
+                _stream_handle(torch, dev, stream), ctypes.byref(chosen), ctypes.byref(shape))
         _check(code)
-        return int(chosen.value)
+        return int(chosen.value), int(shape.value)
+
+    @property
+    def shape(self) -> int:
+        """Launch shape of this plan's launches (pf_plan_shape)."""
+        return int(self._lib.pf_plan_shape(self._h))
 
     @property
     def tile_h(self) -> int:
@@ -262,9 +270,10 @@ _plan_cache_lock = threading.Lock()
 
 
 def get_plan(intrinsics, height, width, window, mode="implicit", precision="fp64",
-             kappa_flag=0.0, disparity_scale=None, min_valid=None, band_height=None) -> Plan:
+             kappa_flag=0.0, disparity_scale=None, min_valid=None, band_height=None,
+             shape=None) -> Plan:
     """Cached plan; disparity_scale (1/Z = D * scale) selects disparity input,
-    min_valid partial windows, band_height a launch shape other than the
+    min_valid partial windows, band_height / shape a launch shape other than the
     built-in one (a derived plan, cached under its own key)."""
     ds = 0.0 if disparity_scale is None else float(disparity_scale)
     mv = 0 if min_valid is None else int(min_valid)
@@ -277,12 +286,14 @@ def get_plan(intrinsics, height, width, window, mode="implicit", precision="fp64
                      flags=FLAG_DISPARITY if disparity_scale is not None else 0,
                      disparity_scale=ds, min_valid=mv)
             _plan_cache[key] = p
-        if band_height is None or int(band_height) == p.tile_h:
+        bh = 0 if band_height is None else int(band_height)
+        sh = -1 if shape is None else int(shape)
+        if (bh == 0 or bh == p.tile_h) and (sh == -1 or sh == p.shape):
             return p
-        dkey = key + (int(band_height),)
+        dkey = key + (bh, sh)
         d = _plan_cache.get(dkey)
         if d is None:
-            d = p.derive(int(band_height))
+            d = p.derive(bh, sh)
             _plan_cache[dkey] = d
         return d
 
@@ -314,7 +325,7 @@ class _on_device:
 
 def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "implicit",
                precision: str = "fp64", kappa_flag: float = 0.0, out=None, stream=None,
-               disparity_scale=None, min_valid=None, band_height=None):
+               disparity_scale=None, min_valid=None, band_height=None, shape=None):
     """Per-pixel plane fits of a depth frame on the GPU.
 
     depth       float32 tensor [H, W] on a HIP device (unit stride along W)
@@ -325,8 +336,8 @@ def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "
     disparity_scale  if given, `depth` holds disparity D with 1/Z = D * disparity_scale
     min_valid   if given (3 <= min_valid < k*k), partial windows: a window is fitted
                 from its valid pixels when at least min_valid are valid
-    band_height output rows per workgroup (e.g. from Plan.autotune); None = the
-                plan's built-in launch shape
+    band_height, shape  output rows per workgroup and launch shape (e.g. from
+                Plan.autotune); None = the plan's built-in launch shape
     Returns (normals, offsets, residuals, status), enqueued on the current stream.
     """
     import torch
@@ -336,7 +347,7 @@ def fit_planes(depth, intrinsics, window: int, valid_mask=None, *, mode: str = "
         raise ValueError("depth must have unit stride along W")
     H, W = depth.shape
     plan = get_plan(intrinsics, H, W, window, mode, precision, kappa_flag, disparity_scale,
-                    min_valid, band_height)
+                    min_valid, band_height, shape)
     dev = depth.device
     mptr, mpitch = None, 0
     if valid_mask is not None:
@@ -498,7 +509,8 @@ def _mask_arg(torch, valid_mask, depth):
 
 def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="implicit",
                      precision="fp64", kappa_flag=0.0, outs=None, stream=None,
-                     disparity_scale=None, min_valid=None, queued=False, workspace=None):
+                     disparity_scale=None, min_valid=None, queued=False, workspace=None,
+                     band_heights=None, shape=None):
     """Per-pixel plane fits of several frames (any sizes, per-frame window sizes)
     in as few kernel launches as possible: up to 32 frames per launch, or with
     queued=True all frames in one persistent launch fed by a work queue
@@ -512,6 +524,9 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
     valid_masks  None or a list of (uint8/bool tensor or None)
     min_valid    None, one value for all frames, or a list of them (partial
                  windows; the frames must be all partial or all full-window)
+    band_heights None, one band height for all frames, or a list of them (e.g.
+                 each frame's Plan.autotune result); shape: one launch shape
+                 for all frames (None = the plans' own, which must agree)
     outs         optional list of (normals, offsets, residuals, status) per frame
     Returns the list of (normals, offsets, residuals, status).
     """
@@ -523,7 +538,8 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
     ks = list(windows) if isinstance(windows, (tuple, list)) else [windows] * n
     masks = list(valid_masks) if valid_masks is not None else [None] * n
     mvs = list(min_valid) if isinstance(min_valid, (tuple, list)) else [min_valid] * n
-    if not (len(intr) == len(ks) == len(masks) == len(mvs) == n):
+    bhs = list(band_heights) if isinstance(band_heights, (tuple, list)) else [band_heights] * n
+    if not (len(intr) == len(ks) == len(masks) == len(mvs) == len(bhs) == n):
         raise ValueError("per-frame argument lists must have one entry per frame")
     dev = depths[0].device
     plans, ios, results, keep = [], (_FrameIO * n)(), [], []
@@ -533,7 +549,7 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
             raise ValueError("all frames must be on one device")
         H, W = d.shape
         p = get_plan(intr[i], H, W, ks[i], mode, precision, kappa_flag, disparity_scale,
-                     mvs[i])
+                     mvs[i], bhs[i], shape)
         plans.append(p)
         mptr, mpitch = _mask_arg(torch, masks[i], d)
         if outs is None:

@@ -53,12 +53,18 @@ namespace {
 constexpr int kBlock = 256;   // threads per workgroup; also the strip width in input columns
 constexpr int kMaxWindow = 63;
 
-// Work split of one round: `rows` output rows go through the vertical phase
-// together, then every thread fits a run of `run` consecutive outputs of one
-// row (kBlock / run runs per row, rows * kBlock / run = kBlock threads).  Short
-// rounds keep the LDS footprint at 32 KB (FP64), so that with 128 VGPRs four
-// workgroups share a CU; measured faster than longer runs (8 x 8) for both
-// solves, whose per-run warm-up the extra occupancy more than pays for.
+// Launch shapes.  Work split of one round: `rows` output rows go through the
+// vertical phase together, then every thread fits a run of `run` consecutive
+// outputs of one row (kBlock / run runs per row, rows * kBlock / run = kBlock
+// threads); `groups` is the number of workgroups per CU the register budget
+// is sized for (four: 128 VGPRs; two: 256).
+//   shape 0: 4 x 4, four workgroups per CU (32 KB of LDS in FP64);
+//   shape 1: 4 x 4, two workgroups per CU (the FP64 explicit solve keeps its
+//            four outputs' stores in registers without spilling);
+//   shape 2: 8 x 8, two workgroups per CU (64 KB of LDS; half the per-run
+//            warm-up and half the barriers per row).
+// Shapes 1 and 2 exist for FP64 implicit and explicit full-window fits (the
+// autotuner's candidates); every other path runs shape 0.
 //
 // LDS layout of one row of window column sums: column i lives at
 // (i % run) * sub + i / run.  In the horizontal phase, where almost all LDS
@@ -67,27 +73,36 @@ constexpr int kMaxWindow = 63;
 // conflicts.  The vertical phase writes each column once per row with a
 // stride of sub between neighbouring threads, which can cost two-way bank
 // conflicts on those writes.
-template <int MODE>
+template <int SHAPE>
 struct Tiling;
 template <>
-struct Tiling<PF_EXPLICIT> {
-  static constexpr int rows = 4, run = 4, sub = 72;
+struct Tiling<0> {
+  static constexpr int rows = 4, run = 4, sub = 72, groups = 4;
 };
 template <>
-struct Tiling<PF_IMPLICIT> {
-  static constexpr int rows = 4, run = 4, sub = 72;
+struct Tiling<1> : Tiling<0> {
+  static constexpr int groups = 2;
 };
 template <>
-struct Tiling<PF_IMPLICIT_LITERAL> : Tiling<PF_IMPLICIT> {};
-constexpr int kPitch = 288;  // LDS entries per row, >= kBlock for both tilings
-static_assert(Tiling<PF_EXPLICIT>::run * Tiling<PF_EXPLICIT>::sub == kPitch, "pitch");
-static_assert(Tiling<PF_IMPLICIT>::run * Tiling<PF_IMPLICIT>::sub == kPitch, "pitch");
-static_assert(Tiling<PF_EXPLICIT>::rows * kBlock / Tiling<PF_EXPLICIT>::run == kBlock, "split");
-static_assert(Tiling<PF_IMPLICIT>::rows * kBlock / Tiling<PF_IMPLICIT>::run == kBlock, "split");
+struct Tiling<2> {
+  static constexpr int rows = 8, run = 8, sub = 36, groups = 2;
+};
+constexpr int kShapes = 3;
+constexpr int kPitch = 288;  // LDS entries per row, >= kBlock for every tiling
+static_assert(Tiling<0>::run * Tiling<0>::sub == kPitch, "pitch");
+static_assert(Tiling<2>::run * Tiling<2>::sub == kPitch, "pitch");
+static_assert(Tiling<0>::rows * kBlock / Tiling<0>::run == kBlock, "split");
+static_assert(Tiling<2>::rows * kBlock / Tiling<2>::run == kBlock, "split");
+constexpr int shape_groups(int shape) {
+  return shape == 0 ? Tiling<0>::groups : shape == 1 ? Tiling<1>::groups : Tiling<2>::groups;
+}
+constexpr int shape_rows(int shape) {
+  return shape == 2 ? Tiling<2>::rows : Tiling<0>::rows;
+}
 
-template <int MODE>
+template <int SHAPE>
 __host__ __device__ inline int lds_index(int i) {
-  using TL = Tiling<MODE>;
+  using TL = Tiling<SHAPE>;
   const unsigned u = unsigned(i);  // i >= 0 always
   return int((u % TL::run) * TL::sub + u / TL::run);
 }
@@ -1109,8 +1124,9 @@ __device__ inline int64_t bwd_ws_offset(const LaunchArgs& la, int jb) {
 
 // Workgroups per CU the register budget is sized for: the forward sweeps
 // (32 KB of LDS) are held to 128 VGPRs so that four waves share a SIMD.
-template <typename T, int MODE, bool BWD, bool PARTIAL>
-constexpr int kMinGroups = (MODE != PF_IMPLICIT_LITERAL && !BWD && !PARTIAL) ? 4 : 1;
+template <typename T, int MODE, bool BWD, bool PARTIAL, int SHAPE = 0>
+constexpr int kMinGroups =
+    (MODE != PF_IMPLICIT_LITERAL && !BWD && !PARTIAL) ? Tiling<SHAPE>::groups : 1;
 
 // Launch-wide parameters of a fit (shared by every frame of a launch).
 struct LaunchCommon {
@@ -1120,12 +1136,13 @@ struct LaunchCommon {
 // One workgroup tile: strip `wg % n_strips`, band `wg / n_strips` of frame
 // `job`.  Called once per workgroup by fit_planes_fused and once per work item
 // by the persistent fit_planes_queued, which share every instruction of it.
-template <typename T, int MODE, bool MASK, bool BWD = false, bool PARTIAL = false>
+template <typename T, int MODE, bool MASK, bool BWD = false, bool PARTIAL = false,
+          int SHAPE = 0>
 __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCommon& lc,
                                          double* gws) {
   static_assert(!PARTIAL || (std::is_same<T, double>::value && !BWD && MODE != PF_IMPLICIT_LITERAL),
                 "partial windows: FP64 forward, implicit or explicit");
-  using TL = Tiling<MODE>;
+  using TL = Tiling<SHAPE>;
   FitArgs a;
   a.depth = job.depth;
   a.mask = job.mask;
@@ -1253,7 +1270,7 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
     }
   }
 
-  const int li = lds_index<MODE>(tid);
+  const int li = lds_index<SHAPE>(tid);
   const int hj = tid / (kBlock / TL::run);      // row of the round this thread fits in the horizontal phase
   const int run = tid % (kBlock / TL::run);
   const int o0 = run * TL::run;    // first output column (strip-relative) of the run
@@ -1304,7 +1321,7 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
       // partial windows: valid-pixel sums of x~, x~^2, y~, x~ y~, y~^2 (x~ = i - base)
       int hxn = 0, hx2n = 0, hyn = 0, hxyn = 0, hy2n = 0;
       auto enter = [&](int i) {
-        const int l = lds_index<MODE>(i);
+        const int l = lds_index<SHAPE>(i);
         const T v = rw[l];
         hw += v;
         hx += T(i - base) * v;
@@ -1321,7 +1338,7 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
         }
       };
       auto leave = [&](int i) {
-        const int l = lds_index<MODE>(i);
+        const int l = lds_index<SHAPE>(i);
         const T v = rw[l];
         hw = hw - v;
         hx = hx - T(i - base) * v;
@@ -1452,13 +1469,16 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
           rp[h] = make_float4(ores[4 * h], ores[4 * h + 1], ores[4 * h + 2], ores[4 * h + 3]);
         }
         if (a.status) {
-          // exactly the run's TL::run status bytes, as one 4-byte word (p is a
+          // exactly the run's TL::run status bytes, as 4-byte words (p is a
           // multiple of 4 and status 4-byte aligned when vec_store is set)
-          static_assert(TL::run == 4, "one 32-bit status word per run");
-          uint32_t word = 0;
+          static_assert(TL::run % 4 == 0, "whole 32-bit status words per run");
 #pragma unroll
-          for (int q = 0; q < TL::run; ++q) word |= uint32_t(ost[q]) << (8 * q);
-          *reinterpret_cast<uint32_t*>(a.status + p) = word;
+          for (int h = 0; h < TL::run / 4; ++h) {
+            uint32_t word = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) word |= uint32_t(ost[4 * h + q]) << (8 * q);
+            reinterpret_cast<uint32_t*>(a.status + p)[h] = word;
+          }
         }
       } else {
 #pragma unroll
@@ -1479,16 +1499,16 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
   }
 }
 
-template <typename T, int MODE, bool MASK, bool BWD = false, bool PARTIAL = false>
-__global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD, PARTIAL>)) void fit_planes_fused(LaunchArgs la) {
+template <typename T, int MODE, bool MASK, bool BWD = false, bool PARTIAL = false, int SHAPE = 0>
+__global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, BWD, PARTIAL, SHAPE>)) void fit_planes_fused(LaunchArgs la) {
   // which job and which of its workgroups (the job table is uniform: scalar loop)
   int jb = 0;
   while (jb + 1 < la.n_jobs && int(blockIdx.x) >= la.jobs[jb + 1].wg_begin) ++jb;
   const LaunchCommon lc = {la.kappa_flag, la.kappa_fp64, la.dscale};
   double* gws = nullptr;
   if constexpr (BWD) gws = la.gws + bwd_ws_offset(la, jb);
-  fit_tile<T, MODE, MASK, BWD, PARTIAL>(la.jobs[jb], int(blockIdx.x) - la.jobs[jb].wg_begin, lc,
-                                        gws);
+  fit_tile<T, MODE, MASK, BWD, PARTIAL, SHAPE>(la.jobs[jb], int(blockIdx.x) - la.jobs[jb].wg_begin,
+                                               lc, gws);
 }
 
 // ---------------------------------------------------------------------------
@@ -1553,8 +1573,8 @@ __device__ inline Job load_job_uniform(const Job* p) {
 // up to kQueueLdsJobs jobs, else read from the table.
 constexpr int kQueueLdsJobs = 256;
 
-template <typename T, int MODE, bool MASK, bool PARTIAL = false>
-__global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, false, PARTIAL>)) void fit_planes_queued(QueueArgs qa) {
+template <typename T, int MODE, bool MASK, bool PARTIAL = false, int SHAPE = 0>
+__global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, false, PARTIAL, SHAPE>)) void fit_planes_queued(QueueArgs qa) {
   __shared__ uint32_t s_item;
   __shared__ int32_t s_begin[kQueueLdsJobs];
   const uint32_t n_items = __builtin_amdgcn_readfirstlane(qa.hdr->n_items);
@@ -1582,7 +1602,7 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, false, PARTIAL>)) void
       ++jb;
     jb = __builtin_amdgcn_readfirstlane(jb);
     const Job job = load_job_uniform(qa.jobs + jb);
-    fit_tile<T, MODE, MASK, false, PARTIAL>(job, int(item) - job.wg_begin, qa.lc, nullptr);
+    fit_tile<T, MODE, MASK, false, PARTIAL, SHAPE>(job, int(item) - job.wg_begin, qa.lc, nullptr);
     if (!ahead && threadIdx.x == 0) next = grid + atomicAdd(&qa.hdr->next, 1u);
     if (threadIdx.x == 0) s_item = next;
     __syncthreads();
@@ -1603,8 +1623,7 @@ __global__ __launch_bounds__(kBlock, (kMinGroups<T, MODE, false, PARTIAL>)) void
 // ---------------------------------------------------------------------------
 template <bool MASK>
 __global__ __launch_bounds__(kBlock) void grad_depth_fused(LaunchArgs la) {
-  constexpr int MODE = PF_IMPLICIT;  // 4-row rounds, runs of 4: five FP64 channels in 46 KB
-  using TL = Tiling<MODE>;
+  using TL = Tiling<0>;  // 4-row rounds, runs of 4: five FP64 channels in 46 KB
   int jb = 0;
   while (jb + 1 < la.n_jobs && int(blockIdx.x) >= la.jobs[jb + 1].wg_begin) ++jb;
   const Job& job = la.jobs[jb];
@@ -1649,7 +1668,7 @@ __global__ __launch_bounds__(kBlock) void grad_depth_fused(LaunchArgs la) {
     load(yb - r + i, c);
     add(lead, c);
   }
-  const int li = lds_index<MODE>(tid);
+  const int li = lds_index<0>(tid);
   const int hj = tid / (kBlock / TL::run), run = tid % (kBlock / TL::run);
   const int o0 = run * TL::run, o1 = min(o0 + TL::run, job.tile_w);
   for (int yg = yb; yg < ye; yg += TL::rows) {
@@ -1682,7 +1701,7 @@ __global__ __launch_bounds__(kBlock) void grad_depth_fused(LaunchArgs la) {
       const int base = o0 + r;
       double h[6] = {0, 0, 0, 0, 0, 0}, g[6] = {0, 0, 0, 0, 0, 0};  // a, e, gx, xgx, gy, ygy
       auto acc = [&](double* s6, int i) {
-        const int l = lds_index<MODE>(i);
+        const int l = lds_index<0>(i);
         const double vx = rgx[l];
         s6[0] += ra[l];
         s6[1] += re[l];
@@ -2193,7 +2212,31 @@ struct pf_plan {
   int k, r;
   double S2, N;
   int tile_w, tile_h, n_strips, n_bands;
+  int shape;  // launch shape (Tiling<shape>)
+  // launch shapes other than 0 exist for FP64 implicit / explicit full-window fits
+  bool shapes_allowed() const {
+    return params.precision == PF_PREC_FP64 && !partial() &&
+           (params.mode == PF_IMPLICIT || params.mode == PF_EXPLICIT);
+  }
 };
+
+namespace {
+// The default band height of a plan for launch shape `shape`: enough
+// workgroups for one full round of the chip (its workgroups per CU on 256 CUs),
+// with at least 8 rows for the explicit solve, whose per-band warm-up and
+// prologue would otherwise outweigh its short per-pixel work.  Rounded up to
+// whole rounds of rows: a band of 4q + 1 rows costs as many rounds as one of
+// 4q + 4, whose fewer workgroups then share the chip (1920x1080, k = 15:
+// 9 -> 12 rows, +10 % implicit, +4 % explicit).
+int64_t default_band_height(const pf_plan* p, int shape) {
+  const int64_t target_groups = 256 * int64_t(shape_groups(shape));
+  const int64_t round_rows = shape_rows(shape);
+  int64_t th = (p->H * p->n_strips + target_groups - 1) / target_groups;
+  th = std::max<int64_t>(th, p->params.mode == PF_EXPLICIT ? 8 : 4);
+  th = (th + round_rows - 1) / round_rows * round_rows;
+  return std::min<int64_t>(th, p->H);
+}
+}  // namespace
 
 extern "C" {
 
@@ -2257,24 +2300,16 @@ pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t widt
   const int tw_max = ((kBlock - (k - 1)) / 4) * 4;
   p->n_strips = int((width + tw_max - 1) / tw_max);
   p->tile_w = int(((width + p->n_strips - 1) / p->n_strips + 3) / 4 * 4);
-  // bands: enough workgroups for one full round of the chip (four resident per
-  // CU on 256 CUs), with at least 8 rows for the explicit solve, whose per-band
-  // warm-up and prologue would otherwise outweigh its short per-pixel work.
-  // Rounded up to whole rounds of rows: a band of 4q + 1 rows costs as many
-  // rounds as one of 4q + 4, whose fewer workgroups then share the chip
-  // (1920x1080, k = 15: 9 -> 12 rows, +10 % implicit, +4 % explicit).
-  const int64_t target_groups = 1024;
-  constexpr int64_t round_rows = Tiling<PF_IMPLICIT>::rows;
-  static_assert(Tiling<PF_EXPLICIT>::rows == round_rows, "one row round for both solves");
-  int64_t th = (height * p->n_strips + target_groups - 1) / target_groups;
-  th = std::max<int64_t>(th, params->mode == PF_EXPLICIT ? 8 : 4);
-  th = (th + round_rows - 1) / round_rows * round_rows;
+  // launch shape: FP64 explicit keeps its run's outputs in registers, which
+  // two workgroups per CU hold without spilling (measured +9 % at 1920x1080,
+  // k = 15); everything else runs four workgroups per CU
+  p->shape = (p->shapes_allowed() && params->mode == PF_EXPLICIT) ? 1 : 0;
+  int64_t th = default_band_height(p, p->shape);
   // tuning override of the band height (rows of output per workgroup)
   if (const char* env = std::getenv("PF_TILE_H")) {
     const long v = std::strtol(env, nullptr, 10);
-    if (v >= 1) th = v;
+    if (v >= 1) th = std::min<int64_t>(v, height);
   }
-  th = std::min<int64_t>(th, height);
   p->tile_h = int(th);
   p->n_bands = int((height + th - 1) / th);
   *out = p;
@@ -2327,7 +2362,8 @@ pf_status check_batch(const pf_plan* const* plans, const pf_frame_io* io, int32_
         p->params.precision != plans[0]->params.precision ||
         p->params.kappa_flag != plans[0]->params.kappa_flag ||
         p->params.kappa_fp64 != plans[0]->params.kappa_fp64 ||
-        p->dscale() != plans[0]->dscale() || p->partial() != plans[0]->partial())
+        p->dscale() != plans[0]->dscale() || p->partial() != plans[0]->partial() ||
+        p->shape != plans[0]->shape)
       return PF_ERR_UNSUPPORTED;
   }
   return PF_OK;
@@ -2394,9 +2430,10 @@ int device_cus() {
 // One persistent launch of the instantiation for (T, MODE, MASK, PARTIAL):
 // grid = resident workgroups of the chip (occupancy x compute units), capped
 // at the number of work items.
-template <typename T, int MODE, bool MASK, bool PARTIAL>
+template <typename T, int MODE, bool MASK, bool PARTIAL, int SHAPE = 0>
 hipError_t launch_queued(const QueueArgs& qa, uint32_t n_items, hipStream_t s) {
-  const void* fn = reinterpret_cast<const void*>(&fit_planes_queued<T, MODE, MASK, PARTIAL>);
+  const void* fn =
+      reinterpret_cast<const void*>(&fit_planes_queued<T, MODE, MASK, PARTIAL, SHAPE>);
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess ||
       per_cu <= 0)
@@ -2405,9 +2442,19 @@ hipError_t launch_queued(const QueueArgs& qa, uint32_t n_items, hipStream_t s) {
     std::fprintf(stderr, "planefit queued launch: %d workgroups per CU x %d CUs, %u items\n",
                  per_cu, device_cus(), n_items);
   const uint32_t grid = std::min<uint32_t>(n_items, uint32_t(per_cu) * uint32_t(device_cus()));
-  hipLaunchKernelGGL((fit_planes_queued<T, MODE, MASK, PARTIAL>), dim3(grid), dim3(kBlock), 0, s,
-                     qa);
+  hipLaunchKernelGGL((fit_planes_queued<T, MODE, MASK, PARTIAL, SHAPE>), dim3(grid), dim3(kBlock),
+                     0, s, qa);
   return hipGetLastError();
+}
+
+template <int SHAPE>
+hipError_t launch_queued_fp64_shape(const QueueArgs& qa, uint32_t n_items, int mode, bool mask,
+                                    hipStream_t s) {
+  if (mode == PF_EXPLICIT)
+    return mask ? launch_queued<double, PF_EXPLICIT, true, false, SHAPE>(qa, n_items, s)
+                : launch_queued<double, PF_EXPLICIT, false, false, SHAPE>(qa, n_items, s);
+  return mask ? launch_queued<double, PF_IMPLICIT, true, false, SHAPE>(qa, n_items, s)
+              : launch_queued<double, PF_IMPLICIT, false, false, SHAPE>(qa, n_items, s);
 }
 
 template <typename T>
@@ -2479,6 +2526,10 @@ pf_status enqueue_queued(const pf_plan* const* plans, const pf_frame_io* io, int
                             : launch_queued<double, PF_EXPLICIT, false, true>(qa, ni, s))
                 : (has_mask ? launch_queued<double, PF_IMPLICIT, true, true>(qa, ni, s)
                             : launch_queued<double, PF_IMPLICIT, false, true>(qa, ni, s));
+    else if (prec == PF_PREC_FP64 && plans[0]->shape == 1)
+      err = launch_queued_fp64_shape<1>(qa, ni, mode, has_mask, s);
+    else if (prec == PF_PREC_FP64 && plans[0]->shape == 2)
+      err = launch_queued_fp64_shape<2>(qa, ni, mode, has_mask, s);
     else if (prec == PF_PREC_FP64)
       err = launch_queued_modes<double>(qa, ni, mode, has_mask, s);
     else if (prec == PF_PREC_FP32)
@@ -2545,6 +2596,16 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
       if (has_mask) PF_LAUNCH(T, PF_IMPLICIT, true); else PF_LAUNCH(T, PF_IMPLICIT, false); \
     }                                                                          \
   } while (0)
+#define PF_LAUNCH_SHAPE(M, K, SH) \
+  hipLaunchKernelGGL((fit_planes_fused<double, M, K, false, false, SH>), grid, block, 0, s, la)
+#define PF_LAUNCH_FP64_SHAPES(SH)                                              \
+  do {                                                                         \
+    if (expl) {                                                                \
+      if (has_mask) PF_LAUNCH_SHAPE(PF_EXPLICIT, true, SH); else PF_LAUNCH_SHAPE(PF_EXPLICIT, false, SH); \
+    } else {                                                                   \
+      if (has_mask) PF_LAUNCH_SHAPE(PF_IMPLICIT, true, SH); else PF_LAUNCH_SHAPE(PF_IMPLICIT, false, SH); \
+    }                                                                          \
+  } while (0)
     if (plans[first]->partial()) {
       if (expl) {
         if (has_mask) hipLaunchKernelGGL((fit_planes_fused<double, PF_EXPLICIT, true, false, true>), grid, block, 0, s, la);
@@ -2556,12 +2617,17 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
     } else if (prec == PF_PREC_FP64 && plans[first]->params.mode == PF_IMPLICIT_LITERAL) {
       if (has_mask) PF_LAUNCH(double, PF_IMPLICIT_LITERAL, true);
       else PF_LAUNCH(double, PF_IMPLICIT_LITERAL, false);
-    } else if (prec == PF_PREC_FP64)
-      PF_LAUNCH_MODES(double);
-    else if (prec == PF_PREC_FP32)
+    } else if (prec == PF_PREC_FP64) {
+      const int shape = plans[first]->shape;
+      if (shape == 1) PF_LAUNCH_FP64_SHAPES(1);
+      else if (shape == 2) PF_LAUNCH_FP64_SHAPES(2);
+      else PF_LAUNCH_MODES(double);
+    } else if (prec == PF_PREC_FP32)
       PF_LAUNCH_MODES(float);
     else
       PF_LAUNCH_MODES(df32);
+#undef PF_LAUNCH_FP64_SHAPES
+#undef PF_LAUNCH_SHAPE
 #undef PF_LAUNCH_MODES
 #undef PF_LAUNCH
     const hipError_t err = hipGetLastError();
@@ -2605,25 +2671,32 @@ pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_p
 
 int32_t pf_plan_band_height(const pf_plan* plan) { return plan ? plan->tile_h : 0; }
 
-pf_status pf_plan_derive(const pf_plan* plan, int32_t band_height, pf_plan** out) {
+pf_status pf_plan_derive(const pf_plan* plan, int32_t band_height, int32_t shape,
+                         pf_plan** out) {
   if (out) *out = nullptr;
   if (!plan || !out) return PF_ERR_NULL;
-  if (band_height < 1) return PF_ERR_SHAPE;
+  if (band_height < 0) return PF_ERR_SHAPE;
+  if (shape < -1 || shape >= kShapes || (shape > 0 && !plan->shapes_allowed()))
+    return PF_ERR_UNSUPPORTED;
   pf_plan* p = new (std::nothrow) pf_plan(*plan);
   if (!p) return PF_ERR_UNSUPPORTED;
-  p->tile_h = int(std::min<int64_t>(band_height, p->H));
+  if (shape >= 0) p->shape = shape;
+  const int64_t th = band_height > 0 ? band_height : default_band_height(p, p->shape);
+  p->tile_h = int(std::min<int64_t>(th, p->H));
   p->n_bands = int((p->H + p->tile_h - 1) / p->tile_h);
   *out = p;
   return PF_OK;
 }
 
+int32_t pf_plan_shape(const pf_plan* plan) { return plan ? plan->shape : -1; }
+
 pf_status pf_plan_autotune(const pf_plan* plan, const float* depth, int64_t depth_pitch,
                            const uint8_t* mask, int64_t mask_pitch, float* normals,
                            float* offsets, float* residuals, uint8_t* status, void* stream,
-                           int32_t* chosen) {
+                           int32_t* chosen_band_height, int32_t* chosen_shape) {
   if (!plan) return PF_ERR_NULL;
   const pf_frame_io f = {depth, depth_pitch, mask, mask_pitch, normals, offsets, residuals, status};
-  // validate the buffers once (and warm the code up) with the plan's own band height
+  // validate the buffers once (and warm the code up) with the plan's own shape
   pf_status st = pf_fit_planes_batch(&plan, &f, 1, stream);
   if (st != PF_OK) return st;
   // candidates run on a private copy: the caller's plan is never written
@@ -2633,27 +2706,32 @@ pf_status pf_plan_autotune(const pf_plan* plan, const float* depth, int64_t dept
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t err = hipEventCreate(&e0);
   if (err == hipSuccess) err = hipEventCreate(&e1);
-  static const int kCandidates[] = {4, 6, 8, 12, 16, 24, 32, 48, 64};
-  int best_h = plan->tile_h;
+  static const int kCandidates[] = {4, 6, 8, 12, 16, 20, 24, 32, 48, 64};
+  int best_h = plan->tile_h, best_shape = plan->shape;
   float best_ms = 0.0f;
-  for (int cand : kCandidates) {
-    if (err != hipSuccess) break;
-    if (cand > plan->H) continue;
-    trial.tile_h = cand;
-    trial.n_bands = int((plan->H + cand - 1) / cand);
-    st = pf_fit_planes_batch(&tp, &f, 1, stream);  // warm-up at this shape
-    if (st != PF_OK) break;
-    err = hipEventRecord(e0, s);
-    for (int rep = 0; rep < 5 && st == PF_OK && err == hipSuccess; ++rep)
-      st = pf_fit_planes_batch(&tp, &f, 1, stream);
-    if (err == hipSuccess) err = hipEventRecord(e1, s);
-    if (err == hipSuccess) err = hipEventSynchronize(e1);
-    float ms = 0.0f;
-    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-    if (st != PF_OK || err != hipSuccess) break;
-    if (best_ms == 0.0f || ms < best_ms) {
-      best_ms = ms;
-      best_h = cand;
+  const int n_shapes = plan->shapes_allowed() ? kShapes : 1;
+  for (int shape = 0; shape < n_shapes && err == hipSuccess && st == PF_OK; ++shape) {
+    for (int cand : kCandidates) {
+      if (err != hipSuccess) break;
+      if (cand > plan->H || cand % shape_rows(shape) != 0) continue;
+      trial.shape = shape;
+      trial.tile_h = cand;
+      trial.n_bands = int((plan->H + cand - 1) / cand);
+      st = pf_fit_planes_batch(&tp, &f, 1, stream);  // warm-up at this shape
+      if (st != PF_OK) break;
+      err = hipEventRecord(e0, s);
+      for (int rep = 0; rep < 5 && st == PF_OK && err == hipSuccess; ++rep)
+        st = pf_fit_planes_batch(&tp, &f, 1, stream);
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (st != PF_OK || err != hipSuccess) break;
+      if (best_ms == 0.0f || ms < best_ms) {
+        best_ms = ms;
+        best_h = cand;
+        best_shape = shape;
+      }
     }
   }
   if (e0) (void)hipEventDestroy(e0);
@@ -2663,7 +2741,8 @@ pf_status pf_plan_autotune(const pf_plan* plan, const float* depth, int64_t dept
     g_last_hip_error = int(err);
     return PF_ERR_HIP;
   }
-  if (chosen) *chosen = best_h;
+  if (chosen_band_height) *chosen_band_height = best_h;
+  if (chosen_shape) *chosen_shape = best_shape;
   return PF_OK;
 }
 

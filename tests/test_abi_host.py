@@ -269,14 +269,12 @@ def test_autotune_argument_checks_return_before_launch():
     code, plan = _create(H=48, W=64, k=5)
     assert code == 0
     fake = ctypes.c_void_p(0x10000)
-    chosen = ctypes.c_int32(-1)
-    assert lib.pf_plan_autotune(None, fake, 64, None, 0, fake, fake, fake, None, None,
-                                ctypes.byref(chosen)) == 1
-    assert lib.pf_plan_autotune(plan, None, 64, None, 0, fake, fake, fake, None, None,
-                                ctypes.byref(chosen)) == 1
-    assert lib.pf_plan_autotune(plan, fake, 60, None, 0, fake, fake, fake, None, None,
-                                ctypes.byref(chosen)) == 5
-    assert chosen.value == -1          # untouched: nothing was launched
+    chosen, shape = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    args = (ctypes.byref(chosen), ctypes.byref(shape))
+    assert lib.pf_plan_autotune(None, fake, 64, None, 0, fake, fake, fake, None, None, *args) == 1
+    assert lib.pf_plan_autotune(plan, None, 64, None, 0, fake, fake, fake, None, None, *args) == 1
+    assert lib.pf_plan_autotune(plan, fake, 60, None, 0, fake, fake, fake, None, None, *args) == 5
+    assert chosen.value == -1 and shape.value == -1   # untouched: nothing was launched
     lib.pf_plan_destroy(plan)
 
 
@@ -284,14 +282,15 @@ def test_autotune_argument_checks_return_before_launch():
     (480, 640, 9, "implicit", 4),      # 3 strips x 480 rows fit one round at the 4-row minimum
     (480, 640, 9, "explicit", 8),      # the explicit minimum
     (1080, 1920, 15, "implicit", 12),  # 8 strips: 9 rows for one round, rounded up to whole 4-row rounds
-    (1080, 1920, 15, "explicit", 12),
+    (1080, 1920, 15, "explicit", 20),  # two workgroups per CU: 17 rows for 512 -> 20
     (1080, 1920, 31, "implicit", 12),  # 9 strips: 10 rows -> 12
     (720, 1280, 5, "implicit", 8),     # 6 strips: 5 rows -> 8
     (30, 40, 3, "implicit", 4),
     (6, 40, 3, "explicit", 6),         # never taller than the frame
 ])
 def test_default_band_height_is_whole_rounds(H, W, k, mode, rows):
-    """The plan's band height: one round of 1,024 workgroups, at least 4 rows
+    """The plan's band height: one round of the chip's workgroup slots (1,024 at
+    four per CU; 512 for the FP64 explicit shape at two per CU), at least 4 rows
     (implicit) or 8 (explicit), rounded up to a multiple of the kernel's 4-row
     round and capped at the frame height."""
     p = pf.Plan((525.0, 525.0, W / 2 - 0.5, H / 2 - 0.5), H, W, k, mode)
@@ -306,17 +305,28 @@ def test_derive_leaves_the_plan_alone():
     assert code == 0
     before = lib.pf_plan_band_height(plan)
     out = ctypes.c_void_p()
-    assert lib.pf_plan_derive(plan, 12, ctypes.byref(out)) == 0
+    assert lib.pf_plan_derive(plan, 12, -1, ctypes.byref(out)) == 0
     assert lib.pf_plan_band_height(out) == 12
     assert lib.pf_plan_band_height(plan) == before
+    assert lib.pf_plan_shape(out) == lib.pf_plan_shape(plan) == 0
     big = ctypes.c_void_p()
-    assert lib.pf_plan_derive(plan, 100000, ctypes.byref(big)) == 0
+    assert lib.pf_plan_derive(plan, 100000, 2, ctypes.byref(big)) == 0
     assert lib.pf_plan_band_height(big) == 480              # clamped to the frame
+    assert lib.pf_plan_shape(big) == 2 and lib.pf_plan_shape(plan) == 0
+    rule = ctypes.c_void_p()
+    assert lib.pf_plan_derive(plan, 0, 1, ctypes.byref(rule)) == 0   # the shape's own rule
+    assert lib.pf_plan_band_height(rule) >= 4
     bad = ctypes.c_void_p(1)
-    assert lib.pf_plan_derive(plan, 0, ctypes.byref(bad)) == 2
+    assert lib.pf_plan_derive(plan, -1, -1, ctypes.byref(bad)) == 2
     assert bad.value is None
-    assert lib.pf_plan_derive(None, 8, ctypes.byref(bad)) == 1
-    for h in (out, big, plan):
+    assert lib.pf_plan_derive(plan, 8, 3, ctypes.byref(bad)) == 8
+    assert lib.pf_plan_derive(None, 8, -1, ctypes.byref(bad)) == 1
+    # shapes 1 and 2 only for FP64 full-window implicit / explicit plans
+    code, p32 = _create(H=480, W=640, k=9, prec=1)
+    assert lib.pf_plan_derive(p32, 8, 2, ctypes.byref(bad)) == 8
+    code, pex = _create(H=480, W=640, k=9, mode=1)
+    assert lib.pf_plan_shape(pex) == 1                      # FP64 explicit default
+    for h in (out, big, rule, plan, p32, pex):
         lib.pf_plan_destroy(h)
 
 

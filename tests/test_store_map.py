@@ -13,23 +13,25 @@ import pytest
 import paper_2103_06644_amd as pf
 
 BLOCK = 256
-ROWS = 4
-RUN = 4
+SHAPES = {0: (4, 4), 1: (4, 4), 2: (8, 8)}   # launch shape -> (rows per round, run)
 
 
-def geometry(H, W, k, mode):
-    """(tile_w, n_strips, tile_h, n_bands) as the plan computes them."""
+def geometry(H, W, k, mode, shape=None, band_height=None):
+    """(tile_w, n_strips, tile_h, n_bands, shape) as the plan computes them."""
     tw_max = ((BLOCK - (k - 1)) // 4) * 4
     n_strips = -(-W // tw_max)
     tile_w = (-(-W // n_strips) + 3) // 4 * 4
     p = pf.Plan((525.0, 525.0, W / 2 - 0.5, H / 2 - 0.5), H, W, k, mode)
+    if shape is not None or band_height is not None:
+        p = p.derive(band_height or 0, -1 if shape is None else shape)
     tile_h = p.tile_h
-    return tile_w, n_strips, tile_h, -(-H // tile_h)
+    return tile_w, n_strips, tile_h, -(-H // tile_h), p.shape
 
 
-def emulate(H, W, k, mode, vec_store):
+def emulate(H, W, k, mode, vec_store, shape=None, band_height=None):
     """Bytes written per status position and per float position (one plane)."""
-    tile_w, n_strips, tile_h, n_bands = geometry(H, W, k, mode)
+    tile_w, n_strips, tile_h, n_bands, shp = geometry(H, W, k, mode, shape, band_height)
+    ROWS, RUN = SHAPES[shp]
     assert tile_w + k - 1 <= BLOCK
     hits = np.zeros(H * W + 64, np.int32)        # +64: room to catch an overrun
     for wg in range(n_strips * n_bands):
@@ -66,5 +68,15 @@ def emulate(H, W, k, mode, vec_store):
 def test_every_pixel_written_once_and_nothing_past_the_end(H, W, k, mode):
     vec = (W % 4 == 0)
     hits = emulate(H, W, k, mode, vec)
+    assert np.all(hits[:H * W] == 1), np.unique(hits[:H * W], return_counts=True)
+    assert not hits[H * W:].any()
+
+
+@pytest.mark.parametrize("shape,bh", [(1, 12), (2, 8), (2, 24), (2, 0), (0, 6)])
+@pytest.mark.parametrize("H,W,k,mode", [(480, 640, 15, "explicit"), (1080, 1920, 31, "implicit"),
+                                        (37, 92, 7, "explicit"), (120, 160, 5, "implicit")])
+def test_every_shape_writes_each_pixel_once(H, W, k, mode, shape, bh):
+    vec = (W % 4 == 0)
+    hits = emulate(H, W, k, mode, vec, shape, bh)
     assert np.all(hits[:H * W] == 1), np.unique(hits[:H * W], return_counts=True)
     assert not hits[H * W:].any()

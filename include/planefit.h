@@ -251,6 +251,23 @@ pf_status pf_fit_planes_batch_queued(const pf_plan* const* plans, const pf_frame
                                      int32_t n, void* workspace, size_t workspace_bytes,
                                      void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): pf_fit_planes_batch_queued
+ * with its queue header and job table in a scratch array of the library's own
+ * static device memory (one array per GPU, about 31 KB, held until the process
+ * ends) instead of a caller's workspace.  It calls no hipMalloc, hipFree or
+ * other allocating routine; the array's device address is resolved once per
+ * device, on the first call with that device current.  n may be at most
+ * pf_batch_noalloc_max_frames() (256; larger n returns PF_ERR_WORKSPACE before
+ * anything is enqueued).  Every call on a GPU shares that GPU's array, which
+ * keeps the last call's table: calls that overlap in time on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.
+ * Arguments, checks and results are otherwise those of
+ * pf_fit_planes_batch_queued. */
+pf_status pf_fit_planes_batch_queued_noalloc(const pf_plan* const* plans, const pf_frame_io* io,
+                                             int32_t n, void* stream);
+int32_t pf_batch_noalloc_max_frames(void);
+
 /* Bytes of device workspace pf_fit_planes_backward needs: 32 * H * W (the four
  * per-window moment gradients in FP64). */
 size_t pf_backward_workspace_bytes(const pf_plan* plan);

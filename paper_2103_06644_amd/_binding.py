@@ -74,6 +74,7 @@ EXPORTS = ("pf_plan_create", "pf_plan_destroy", "pf_plan_workspace_bytes", "pf_p
            "pf_plan_band_height", "pf_plan_derive", "pf_plan_shape",
            "pf_plan_camera_moments", "pf_fit_planes", "pf_fit_planes_batch",
            "pf_batch_workspace_bytes", "pf_fit_planes_batch_queued",
+           "pf_fit_planes_batch_queued_noalloc", "pf_batch_noalloc_max_frames",
            "pf_backward_workspace_bytes", "pf_fit_planes_backward",
            "pf_fit_planes_backward_batch", "pf_fit_planes_xyz",
            "pf_integral_workspace_bytes", "pf_integral_images", "pf_fit_rects",
@@ -111,6 +112,11 @@ def load_library(path: str | None = None):
         lib.pf_fit_planes_batch_queued.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_FrameIO), i32,
                                                    vp, ctypes.c_size_t, vp]
         lib.pf_fit_planes_batch_queued.restype = i32
+        lib.pf_fit_planes_batch_queued_noalloc.argtypes = [ctypes.POINTER(vp),
+                                                           ctypes.POINTER(_FrameIO), i32, vp]
+        lib.pf_fit_planes_batch_queued_noalloc.restype = i32
+        lib.pf_batch_noalloc_max_frames.argtypes = []
+        lib.pf_batch_noalloc_max_frames.restype = i32
         lib.pf_plan_band_height.argtypes = [vp]
         lib.pf_plan_band_height.restype = i32
         lib.pf_plan_autotune.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp,
@@ -516,7 +522,10 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
     queued=True all frames in one persistent launch fed by a work queue
     (pf_fit_planes_batch_queued; `workspace` optionally a uint8 device tensor of
     at least pf_batch_workspace_bytes(n) bytes, 256-byte aligned, else one is
-    allocated).
+    allocated).  workspace="static" uses the library's own static device
+    scratch instead (pf_fit_planes_batch_queued_noalloc: no device allocation;
+    at most pf_batch_noalloc_max_frames() frames; calls on one GPU must not
+    overlap in time).
 
     depths       list of float32 [H_i, W_i] tensors on one HIP device
     intrinsics   one (fx, fy, cx, cy) for all frames, or a list of them
@@ -566,7 +575,12 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
     handles = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
     lib = load_library()
     with _on_device(torch, dev):
-        if queued:
+        if queued and isinstance(workspace, str):
+            if workspace != "static":
+                raise ValueError('workspace must be a device tensor, None or "static"')
+            code = lib.pf_fit_planes_batch_queued_noalloc(handles, ios, n,
+                                                          _stream_handle(torch, dev, stream))
+        elif queued:
             need = int(lib.pf_batch_workspace_bytes(n))
             if workspace is None:
                 workspace = torch.empty(need, dtype=torch.uint8, device=dev)

@@ -45,6 +45,7 @@
 #include <type_traits>
 #include <vector>
 #include <atomic>
+#include <mutex>
 
 #include "planefit.h"
 
@@ -2544,6 +2545,44 @@ pf_status enqueue_queued(const pf_plan* const* plans, const pf_frame_io* io, int
   return PF_OK;
 }
 
+// Scratch of the allocation-free queued batch (pf_fit_planes_batch_queued_noalloc):
+// the queue header and the job table of up to kNoAllocJobs frames, one copy per
+// GPU the library runs on, held until the process ends.  In host code the
+// array's name is only a host-side stand-in: its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr int kNoAllocJobs = 256;
+constexpr size_t kNoAllocScratchBytes =
+    (kQueueHeaderBytes + size_t(kNoAllocJobs) * sizeof(Job) + 255) / 256 * 256;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (PF_ERR_HIP if the
+// runtime cannot resolve it).
+pf_status scratch_for_current_device(void** out) {
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) {
+    g_last_hip_error = int(err);
+    return PF_ERR_HIP;
+  }
+  if (dev < 0 || dev >= kMaxDevices) return PF_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (err != hipSuccess || !p) {
+      g_last_hip_error = int(err != hipSuccess ? err : hipErrorInvalidSymbol);
+      return PF_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2657,6 +2696,21 @@ pf_status pf_fit_planes_batch_queued(const pf_plan* const* plans, const pf_frame
   std::vector<int32_t> order(static_cast<size_t>(n), 0);
   return enqueue_queued(plans, io, n, workspace, stream, jobs.data(), order.data());
 }
+
+pf_status pf_fit_planes_batch_queued_noalloc(const pf_plan* const* plans, const pf_frame_io* io,
+                                             int32_t n, void* stream) {
+  const pf_status chk = check_batch(plans, io, n);
+  if (chk != PF_OK || n == 0) return chk;
+  if (n > kNoAllocJobs) return PF_ERR_WORKSPACE;
+  void* ws = nullptr;
+  const pf_status st = scratch_for_current_device(&ws);
+  if (st != PF_OK) return st;
+  Job jobs[kNoAllocJobs];
+  int32_t order[kNoAllocJobs];
+  return enqueue_queued(plans, io, n, ws, stream, jobs, order);
+}
+
+int32_t pf_batch_noalloc_max_frames(void) { return kNoAllocJobs; }
 
 pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_pitch,
                         const uint8_t* mask, int64_t mask_pitch, float* normals,

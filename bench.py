@@ -307,9 +307,10 @@ def xyz_measure(torch, pf, frames_for):
 
 def rects_measure(torch, pf, np, frames_for):
     """Fits to many rectangles of one 1080p frame (the paper's use of integral
-    images, Sec. II-C): the FP64 integral images of the frame (five launches),
-    then 100,000 seeded rectangles of 8..128 pixels a side, implicit and
-    explicit; each timed over graph replays."""
+    images, Sec. II-C): the FP64 integral images of the frame (three launches;
+    44 algorithmic bytes per pixel: the depth in, five FP64 planes out), then
+    100,000 seeded rectangles of 8..128 pixels a side, implicit and explicit;
+    each timed over graph replays."""
     f = frames_for("hd_1920x1080")[0]
     H, W = f.depth.shape
     d = torch.from_numpy(f.depth).cuda()
@@ -349,6 +350,8 @@ def rects_measure(torch, pf, np, frames_for):
             ms = a.elapsed_time(b) / 50
             res[f"{mode}_{name}_ms"] = round(ms, 5)
         res[f"{mode}_Mrects_s"] = round(n / (res[f"{mode}_rects_ms"] * 1e-3) / 1e6, 1)
+        res[f"{mode}_integral_hbm_frac"] = round(
+            44.0 * H * W / (res[f"{mode}_integral_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     return res
 
 

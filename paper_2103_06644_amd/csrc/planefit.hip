@@ -515,6 +515,59 @@ struct PixelOut {
   float kappa;  // implicit: l3 / (l2 - l1) of the 3x3 (inf when degenerate)
 };
 
+// ---------------------------------------------------------------------------
+// Output stores of the horizontal phase through buffer resources.  A wave fits
+// ROWS consecutive output rows of one strip (one for runs of 4, two for runs
+// of 8); its resources start at the first of them, and a lane's offset is
+// replaced by one far past the range when its pixel lies outside the strip,
+// the frame or the band, which makes the hardware drop the store.  No branch
+// guards a store, so the compiler counts every one of them as issued.
+// ---------------------------------------------------------------------------
+constexpr int kBufferWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
+constexpr uint32_t kDropOffset = 0x80000000u;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int ROWS>
+struct RowOut {
+  __amdgpu_buffer_rsrc_t n0, n1, n2, d, r, st;
+  int base;  // this lane's row within the wave's rows, times W
+
+  __device__ static __amdgpu_buffer_rsrc_t rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, int(bytes), kBufferWord3);
+  }
+  // hj: this lane's row of the round; nr: rows of the round inside the band
+  __device__ RowOut(const FitArgs& a, int yg, int hj, int nr, int ox0, int& cols) {
+    const int h0 = __builtin_amdgcn_readfirstlane(hj);
+    const int64_t p = int64_t(min(yg + h0, a.H - 1)) * a.W + ox0;
+    const uint32_t n = uint32_t(ROWS) * uint32_t(a.W);
+    n0 = rsrc(a.normals + p, 4 * n);
+    n1 = rsrc(a.normals + a.plane + p, 4 * n);
+    n2 = rsrc(a.normals + 2 * a.plane + p, 4 * n);
+    d = rsrc(a.offsets + p, 4 * n);
+    r = rsrc(a.residuals + p, 4 * n);
+    st = a.status ? rsrc(a.status + p, n) : rsrc(a.offsets, 0u);
+    base = (hj - h0) * a.W;
+    cols = hj < nr ? min(a.tile_w, a.W - ox0) : 0;
+  }
+  // element offset of strip column c, or the drop offset
+  __device__ uint32_t at(int c, int cols) const { return c < cols ? uint32_t(base + c) : kDropOffset; }
+  __device__ void put(uint32_t e, const PixelOut& po) const {
+    const uint32_t b = e == kDropOffset ? kDropOffset : 4u * e;
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(po.n0), n0, int(b), 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(po.n1), n1, int(b), 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(po.n2), n2, int(b), 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(po.d), d, int(b), 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(po.res), r, int(b), 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b8(po.st, st, int(e), 0, 0);
+  }
+  __device__ static void put4(__amdgpu_buffer_rsrc_t res, uint32_t e, const float* v) {
+    const uint32_t b = e == kDropOffset ? kDropOffset : 4u * e;
+    const u32x4 w = {__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                     __float_as_uint(v[3])};
+    __builtin_amdgcn_raw_buffer_store_b128(w, res, int(b), 0, 0);
+  }
+};
+
 __device__ inline PixelOut invalid_pixel() {
   PixelOut o;
   const float nan = __builtin_nanf("");
@@ -1274,9 +1327,13 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
   const int li = lds_index<SHAPE>(tid);
   const int hj = tid / (kBlock / TL::run);      // row of the round this thread fits in the horizontal phase
   const int run = tid % (kBlock / TL::run);
-  const int o0 = run * TL::run;    // first output column (strip-relative) of the run
+  const int o0s = run * TL::run;   // first output column (strip-relative) of the run
+  // Forward launches run the horizontal phase on every lane: a lane whose run
+  // lies past the strip computes the strip's last run again, and its stores
+  // land outside the row's buffer range, which the hardware drops.
+  const int o0 = BWD ? o0s : min(o0s, (a.tile_w - 1) / TL::run * TL::run);
   const int o1 = min(o0 + TL::run, a.tile_w);
-  const bool vec_store = a.vec_store != 0;
+  const bool vec_store = __builtin_amdgcn_readfirstlane(a.vec_store) != 0;  // uniform per job
 
   for (int yg = yb; yg < ye; yg += TL::rows) {
     const int nr = min(TL::rows, ye - yg);
@@ -1308,8 +1365,10 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
       }
     }
     __syncthreads();
-    // horizontal phase: a run of TL::run outputs along one row
-    if (hj < nr && o0 < o1) {
+    // horizontal phase: a run of TL::run outputs along one row (forward
+    // launches: every lane of every row, see above; a row past the band reads
+    // stale column sums and stores nothing)
+    if (BWD ? (hj < nr && o0 < o1) : true) {
       const int y0 = yg + hj;
       const T* rw = sw + hj * kPitch;
       const T* ryw = syw + hj * kPitch;
@@ -1425,75 +1484,59 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
           a.gws[2 * a.plane + pp] = mg.Sy;
           a.gws[3 * a.plane + pp] = mg.Sww;
         }
-      } else if (MODE != PF_EXPLICIT) {
-        // the eigen-solve is large: keep the loop rolled and store each pixel directly
-        const int64_t prow = (int64_t)y0 * a.W + ox0;
+      } else {
+        // Stores through per-row buffer ranges: a pixel past the strip, the
+        // frame or the band falls outside the range and the hardware drops its
+        // store, so no branch guards a store.  The vector memory counter
+        // retires in issue order, so the wait for the next round's depth loads
+        // (issued before this phase) then counts these stores as issued
+        // later and does not wait for them to complete.
+        int cols;
+        const RowOut<TL::run / 4> ro(a, yg, hj, nr, ox0, cols);
+        if constexpr (MODE != PF_EXPLICIT) {
+          // one pixel at a time, each stored as soon as it is solved (the
+          // eigen-solve is large: the loop stays rolled)
 #pragma unroll 1
-        for (int q = 0; q < o1 - o0; ++q) {
-          const PixelOut po = step(q);
-          const int64_t pp = prow + o0 + q;
-          if (ox0 + o0 + q < a.W) {
-            a.normals[pp] = po.n0;
-            a.normals[a.plane + pp] = po.n1;
-            a.normals[2 * a.plane + pp] = po.n2;
-            a.offsets[pp] = po.d;
-            a.residuals[pp] = po.res;
-            if (a.status) a.status[pp] = po.st;
+          for (int q = 0; q < TL::run; ++q) {
+            const PixelOut po = step(q);
+            ro.put(ro.at(o0s + q, cols), po);
+          }
+        } else {
+          float on0[TL::run], on1[TL::run], on2[TL::run], od[TL::run], ores[TL::run];
+          uint8_t ost[TL::run];
+#pragma unroll
+          for (int q = 0; q < TL::run; ++q) {
+            const PixelOut po = step(q);
+            on0[q] = po.n0; on1[q] = po.n1; on2[q] = po.n2; od[q] = po.d; ores[q] = po.res;
+            ost[q] = po.st;
+          }
+          if (vec_store) {
+            // W, tile_w and o0s are multiples of 4, so a group of four is wholly
+            // inside the row's range or wholly outside it
+            static_assert(TL::run % 4 == 0, "whole 16-byte groups per run");
+#pragma unroll
+            for (int h = 0; h < TL::run / 4; ++h) {
+              const uint32_t e = ro.at(o0s + 4 * h, cols);
+              ro.put4(ro.n0, e, on0 + 4 * h);
+              ro.put4(ro.n1, e, on1 + 4 * h);
+              ro.put4(ro.n2, e, on2 + 4 * h);
+              ro.put4(ro.d, e, od + 4 * h);
+              ro.put4(ro.r, e, ores + 4 * h);
+              uint32_t word = 0;
+#pragma unroll
+              for (int q = 0; q < 4; ++q) word |= uint32_t(ost[4 * h + q]) << (8 * q);
+              __builtin_amdgcn_raw_buffer_store_b32(word, ro.st, int(e), 0, 0);
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < TL::run; ++q) {
+              PixelOut po;
+              po.n0 = on0[q]; po.n1 = on1[q]; po.n2 = on2[q]; po.d = od[q]; po.res = ores[q];
+              po.st = ost[q];
+              ro.put(ro.at(o0s + q, cols), po);
+            }
           }
         }
-      } else {
-      float on0[TL::run], on1[TL::run], on2[TL::run], od[TL::run], ores[TL::run];
-      uint8_t ost[TL::run];
-#pragma unroll
-      for (int q = 0; q < TL::run; ++q) {
-        if (o0 + q < o1) {
-          const PixelOut po = step(q);
-          on0[q] = po.n0; on1[q] = po.n1; on2[q] = po.n2; od[q] = po.d; ores[q] = po.res;
-          ost[q] = po.st;
-        }
-      }
-      const int x0 = ox0 + o0;
-      const int64_t p = (int64_t)y0 * a.W + x0;
-      if (vec_store && o0 + TL::run <= o1 && x0 + TL::run <= a.W) {
-        // 16-byte aligned: W and tile_w are multiples of 4, and so is o0
-        float4* n0p = reinterpret_cast<float4*>(a.normals + p);
-        float4* n1p = reinterpret_cast<float4*>(a.normals + a.plane + p);
-        float4* n2p = reinterpret_cast<float4*>(a.normals + 2 * a.plane + p);
-        float4* dp = reinterpret_cast<float4*>(a.offsets + p);
-        float4* rp = reinterpret_cast<float4*>(a.residuals + p);
-#pragma unroll
-        for (int h = 0; h < TL::run / 4; ++h) {
-          n0p[h] = make_float4(on0[4 * h], on0[4 * h + 1], on0[4 * h + 2], on0[4 * h + 3]);
-          n1p[h] = make_float4(on1[4 * h], on1[4 * h + 1], on1[4 * h + 2], on1[4 * h + 3]);
-          n2p[h] = make_float4(on2[4 * h], on2[4 * h + 1], on2[4 * h + 2], on2[4 * h + 3]);
-          dp[h] = make_float4(od[4 * h], od[4 * h + 1], od[4 * h + 2], od[4 * h + 3]);
-          rp[h] = make_float4(ores[4 * h], ores[4 * h + 1], ores[4 * h + 2], ores[4 * h + 3]);
-        }
-        if (a.status) {
-          // exactly the run's TL::run status bytes, as 4-byte words (p is a
-          // multiple of 4 and status 4-byte aligned when vec_store is set)
-          static_assert(TL::run % 4 == 0, "whole 32-bit status words per run");
-#pragma unroll
-          for (int h = 0; h < TL::run / 4; ++h) {
-            uint32_t word = 0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) word |= uint32_t(ost[4 * h + q]) << (8 * q);
-            reinterpret_cast<uint32_t*>(a.status + p)[h] = word;
-          }
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < TL::run; ++q) {
-          if (o0 + q < o1 && x0 + q < a.W) {
-            a.normals[p + q] = on0[q];
-            a.normals[a.plane + p + q] = on1[q];
-            a.normals[2 * a.plane + p + q] = on2[q];
-            a.offsets[p + q] = od[q];
-            a.residuals[p + q] = ores[q];
-            if (a.status) a.status[p + q] = ost[q];
-          }
-        }
-      }
       }
     }
     __syncthreads();
@@ -1919,16 +1962,33 @@ __global__ __launch_bounds__(kBlock) void fit_planes_xyz(LaunchArgs la) {
 // of integral images (Sec. II-C), for fits to many regions of one frame (tiles,
 // segmentation candidates) rather than to every pixel's window.
 //
-// Workspace: a 256-byte header (the frame's reference disparity w_ref at [0]),
-// then five FP64 planes I[c][H+1][W+1] with a zero first row and column,
+// Workspace (doubles): a 256-byte header (the frame's reference disparity
+// w_ref at [0]), then five planes I[c][H+1][W+1] with a zero first row and
+// column,
 //   c = 0: w^ = w - w_ref,  1: x~ w^,  2: y~ w^,  3: w^2,  4: valid count,
 // summed over valid pixels, with x~ = x - W/2 and y~ = y - H/2 (integers; the
 // centring halves the magnitude of the prefix sums a corner difference cancels),
-// then the column
-// totals of each band of kIntBand rows (5 [n_bands][W+1] planes), scanned in
-// place to the sum of the bands above.
+// then the tile aggregates the build carries between tiles:
+//   CT[c][band][W]   column totals of each band of kIntBand rows, scanned to
+//                    the sum of the bands above,
+//   RT[c][strip][H]  row totals of each strip of kBlock columns, scanned to the
+//                    sum of the strips to the left.
+//
+// Three launches, each reading the depth at most once and writing each plane
+// entry once:
+//   integral_tiles  per tile (strip x band): its column totals and row totals;
+//   integral_carry  the two exclusive scans of those totals;
+//   integral_final  per tile: the tile's own 2D prefix (a running column sum
+//                   of row scans) plus its carries.  With Cb[x] the scanned
+//                   column total of the tile's band and Rs[y] the scanned row
+//                   total of its strip, a pixel (x, y) of the tile at (x0, y0)
+//     I[y+1][x+1] = sum_{x' < x0} Cb[x'] + sum_{x0 <= x' <= x} Cb[x']
+//                 + sum_{y0 <= y' <= y} Rs[y'] + sum_{y0 <= y' <= y, x0 <= x' <= x} v.
+// Every workgroup computes w_ref itself from the middle row (the same
+// reduction in the same order, so the same value).
 // ---------------------------------------------------------------------------
 constexpr int kIntBand = 16;
+constexpr int kIntWaves = kBlock / 64;
 constexpr int64_t kIntHeader = 32;  // doubles (256 bytes)
 
 struct IntegralArgs {
@@ -1939,27 +1999,60 @@ struct IntegralArgs {
   double* ws;
 };
 
-__device__ inline int64_t int_plane(const IntegralArgs& ia) {
-  return int64_t(ia.H + 1) * (ia.W + 1);
+struct IntegralLayout {
+  int64_t ld, P;       // plane row length (W + 1) and plane size
+  int n_strips, n_bands;
+  double* I;           // the five planes
+  double* CT;          // [5][n_bands][W]
+  double* RT;          // [5][n_strips][H]
+  double* WT;          // [n_bands][n_strips][kIntBand][kIntWaves][5]: each wave's row totals
+  __device__ explicit IntegralLayout(const IntegralArgs& ia) {
+    ld = ia.W + 1;
+    P = int64_t(ia.H + 1) * ld;
+    n_strips = (ia.W + kBlock - 1) / kBlock;
+    n_bands = (ia.H + kIntBand - 1) / kIntBand;
+    I = ia.ws + kIntHeader;
+    CT = I + 5 * P;
+    RT = CT + int64_t(5) * n_bands * ia.W;
+    WT = RT + int64_t(5) * n_strips * ia.H;
+  }
+  __device__ double* tile_wt(int s, int b) const {
+    return WT + (int64_t(b) * n_strips + s) * (kIntBand * kIntWaves * 5);
+  }
+};
+
+// depth of pixel (x, y), clamped into the frame: every load is in bounds and
+// none sits behind a branch, so a batch of them is issued back to back
+__device__ inline float int_depth(const IntegralArgs& ia, int x, int y) {
+  return ia.depth[int64_t(min(y, ia.H - 1)) * ia.depth_pitch + min(x, ia.W - 1)];
+}
+__device__ inline uint8_t int_mask(const IntegralArgs& ia, int x, int y) {
+  return ia.mask[int64_t(min(y, ia.H - 1)) * ia.mask_pitch + min(x, ia.W - 1)];
 }
 
-__device__ inline float int_load(const IntegralArgs& ia, int x, int y) {
-  float z = ia.depth[int64_t(y) * ia.depth_pitch + x];
-  if (ia.mask && ia.mask[int64_t(y) * ia.mask_pitch + x] == 0) z = 0.0f;
-  return z;
-}
-
-// the frame's reference disparity: mean valid w of the middle row (one workgroup)
-__global__ __launch_bounds__(kBlock) void integral_ref(IntegralArgs ia) {
-  __shared__ double red[2 * (kBlock / 64)];
+// the frame's reference disparity: mean valid w of the middle row, reduced by
+// the whole workgroup in a fixed order
+__device__ inline double integral_wref(const IntegralArgs& ia, double* red) {
   const int tid = threadIdx.x, y = ia.H / 2;
+  constexpr int kBatch = 8;
   double s = 0.0, c = 0.0;
-  for (int x = tid; x < ia.W; x += kBlock) {
-    const float z = int_load(ia, x, y);
-    if (depth_valid(z)) {
-      s += 1.0 / double(z);
-      c += 1.0;
+  for (int x0 = tid; x0 < ia.W; x0 += kBatch * kBlock) {
+    float z[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) z[j] = int_depth(ia, x0 + j * kBlock, y);
+    if (ia.mask) {
+      uint8_t m[kBatch];
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j) m[j] = int_mask(ia, x0 + j * kBlock, y);
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j) z[j] = m[j] ? z[j] : 0.0f;
     }
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j)
+      if (x0 + j * kBlock < ia.W && depth_valid(z[j])) {
+        s += 1.0 / double(z[j]);
+        c += 1.0;
+      }
   }
   for (int off = 32; off > 0; off >>= 1) {
     s += __shfl_down(s, off, 64);
@@ -1970,129 +2063,277 @@ __global__ __launch_bounds__(kBlock) void integral_ref(IntegralArgs ia) {
     red[2 * (tid >> 6) + 1] = c;
   }
   __syncthreads();
-  if (tid == 0) {
-    double ts = 0.0, tc = 0.0;
-    for (int i = 0; i < kBlock / 64; ++i) {
-      ts += red[2 * i];
-      tc += red[2 * i + 1];
-    }
-    ia.ws[0] = tc > 0.0 ? ts / tc : 0.0;
+  double ts = 0.0, tc = 0.0;
+  for (int i = 0; i < kIntWaves; ++i) {
+    ts += red[2 * i];
+    tc += red[2 * i + 1];
+  }
+  __syncthreads();
+  return tc > 0.0 ? ts / tc : 0.0;
+}
+
+// the band's depth samples of column x (0 outside the frame or the band, and
+// where masked), all loads issued before any is used
+__device__ inline void load_band(const IntegralArgs& ia, int x, int y0, int y1, float z[kIntBand]) {
+#pragma unroll
+  for (int j = 0; j < kIntBand; ++j) z[j] = int_depth(ia, x, y0 + j);
+  if (ia.mask) {
+    uint8_t m[kIntBand];
+#pragma unroll
+    for (int j = 0; j < kIntBand; ++j) m[j] = int_mask(ia, x, y0 + j);
+#pragma unroll
+    for (int j = 0; j < kIntBand; ++j) z[j] = m[j] ? z[j] : 0.0f;
+  }
+#pragma unroll
+  for (int j = 0; j < kIntBand; ++j) z[j] = (x < ia.W && y0 + j < y1) ? z[j] : 0.0f;
+}
+
+// the five integrands of pixel (x, y) with depth z; zero outside the frame and
+// where invalid
+__device__ inline void integrands(const IntegralArgs& ia, int x, int y, float z, double wref,
+                                  double v[5]) {
+  for (int c = 0; c < 5; ++c) v[c] = 0.0;
+  if (x < ia.W && depth_valid(z)) {
+    const double wh = 1.0 / double(z) - wref;
+    v[0] = wh;
+    v[1] = double(x - ia.W / 2) * wh;
+    v[2] = double(y - ia.H / 2) * wh;
+    v[3] = wh * wh;
+    v[4] = 1.0;
   }
 }
 
-// row prefix sums: one workgroup per image row, 256-column tiles, wave scans
-__global__ __launch_bounds__(kBlock) void integral_rows(IntegralArgs ia) {
-  __shared__ double tot[kBlock / 64][5];
+// Inclusive prefix sum over the 64 lanes of a wave from DPP lane moves (row
+// shifts by 1, 2, 4, 8 within rows of 16 lanes, then the broadcasts of lane
+// 15 of each row to the next row and of lane 31 to the upper half): six
+// dependent steps with no LDS round trip.  Doubles move as two 32-bit halves.
+template <int CTRL>
+__device__ inline int dpp_move(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const uint64_t b = uint64_t(__double_as_longlong(v));
+  const int lo = dpp_move<CTRL>(int(uint32_t(b)));
+  const int hi = dpp_move<CTRL>(int(uint32_t(b >> 32)));
+  return __longlong_as_double(int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
+}
+
+template <typename V>
+__device__ inline V wave_scan_add(V v) {
+  const int lane = int(threadIdx.x) & 63, rl = lane & 15;
+  V t = dpp_move<0x111>(v);  // row_shr:1
+  v = rl >= 1 ? v + t : v;
+  t = dpp_move<0x112>(v);    // row_shr:2
+  v = rl >= 2 ? v + t : v;
+  t = dpp_move<0x114>(v);    // row_shr:4
+  v = rl >= 4 ? v + t : v;
+  t = dpp_move<0x118>(v);    // row_shr:8
+  v = rl >= 8 ? v + t : v;
+  t = dpp_move<0x142>(v);    // row_bcast:15
+  v = (lane & 31) >= 16 ? v + t : v;
+  t = dpp_move<0x143>(v);    // row_bcast:31
+  v = lane >= 32 ? v + t : v;
+  return v;
+}
+
+// Within-wave row prefix of the five integrands.  y~ w^ (channel 2) is y~
+// times w^ along a row, so its prefix is y~ times channel 0's and is not
+// scanned; the valid count (channel 4) is scanned as an integer.
+__device__ inline void wave_row_scan(const double v[5], double yt, double r[5]) {
+  r[0] = wave_scan_add(v[0]);
+  r[1] = wave_scan_add(v[1]);
+  r[3] = wave_scan_add(v[3]);
+  r[4] = double(wave_scan_add(int(v[4])));
+  r[2] = yt * r[0];
+}
+
+// per tile: column totals over the band; row totals over the strip and each
+// wave's share of them
+__global__ __launch_bounds__(kBlock) void integral_tiles(IntegralArgs ia) {
+  __shared__ double red[2 * kIntWaves];
+  __shared__ double part[kIntBand][kIntWaves][5];  // per row, per wave
+  const IntegralLayout L(ia);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int y = int(blockIdx.x);
-  const int64_t P = int_plane(ia), ld = ia.W + 1;
-  double* I = ia.ws + kIntHeader;
-  const double wref = ia.ws[0];
-  if (tid == 0)
-    for (int c = 0; c < 5; ++c) I[c * P + int64_t(y + 1) * ld] = 0.0;
-  if (y == 0)
-    for (int x = tid; x <= ia.W; x += kBlock)
-      for (int c = 0; c < 5; ++c) I[c * P + x] = 0.0;
-  double carry[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int base = 0; base < ia.W; base += kBlock) {
-    const int x = base + tid;
-    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (x < ia.W) {
-      const float z = int_load(ia, x, y);
-      if (depth_valid(z)) {
-        const double wh = 1.0 / double(z) - wref;
-        v[0] = wh;
-        v[1] = double(x - ia.W / 2) * wh;
-        v[2] = double(y - ia.H / 2) * wh;
-        v[3] = wh * wh;
-        v[4] = 1.0;
-      }
-    }
+  const int s = int(blockIdx.x), b = int(blockIdx.y);
+  const int x = s * kBlock + tid;
+  const int y0 = b * kIntBand, y1 = min(y0 + kIntBand, ia.H);
+  float z[kIntBand];
+  load_band(ia, x, y0, y1, z);
+  const double wref = integral_wref(ia, red);
+  double cs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-#pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        const double o = __shfl_up(v[c], off, 64);
-        if (lane >= off) v[c] += o;
-      }
-    }
+  for (int j = 0; j < kIntBand; ++j) {
+    const int y = y0 + j;
+    if (y >= y1) break;
+    double v[5], r[5];
+    integrands(ia, x, y, z[j], wref, v);
+    for (int c = 0; c < 5; ++c) cs[c] += v[c];
+    wave_row_scan(v, double(y - ia.H / 2), r);
     if (lane == 63)
-      for (int c = 0; c < 5; ++c) tot[wave][c] = v[c];
-    __syncthreads();
+      for (int c = 0; c < 5; ++c) part[j][wave][c] = r[c];
+  }
+  if (x < ia.W)
+    for (int c = 0; c < 5; ++c) L.CT[(int64_t(c) * L.n_bands + b) * ia.W + x] = cs[c];
+  __syncthreads();
+  double* wt = L.tile_wt(s, b);
+  for (int i = tid; i < (y1 - y0) * kIntWaves * 5; i += kBlock) wt[i] = (&part[0][0][0])[i];
+  for (int i = tid; i < (y1 - y0) * 5; i += kBlock) {
+    const int r = i / 5, c = i % 5;
+    double t = 0.0;
+    for (int w = 0; w < kIntWaves; ++w) t += part[r][w][c];
+    L.RT[(int64_t(c) * L.n_strips + s) * ia.H + y0 + r] = t;
+  }
+}
+
+// Exclusive scans of the tile totals: column totals down the bands (four
+// lanes per column, each over a quarter of the bands, joined by a four-lane
+// scan) and row totals across the strips (one thread per row and channel).
+constexpr int kCarryLanes = 4;
+__global__ __launch_bounds__(kBlock) void integral_carry(IntegralArgs ia) {
+  const IntegralLayout L(ia);
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t ncol = int64_t(5) * ia.W * kCarryLanes;
+  if (i < ncol) {  // ncol is a multiple of 4, so a group of four lanes is never split
+    const int q = int(i % kCarryLanes);
+    const int64_t col = i / kCarryLanes;
+    const int c = int(col / ia.W), x = int(col % ia.W);
+    double* T = L.CT + int64_t(c) * L.n_bands * ia.W + x;
+    const int per = (L.n_bands + kCarryLanes - 1) / kCarryLanes;
+    const int bb = min(q * per, L.n_bands), be = min(bb + per, L.n_bands);
+    double part = 0.0;
+    for (int b0 = bb; b0 < be; b0 += 32) {
+      double v[32];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) v[j] = (b0 + j < be) ? T[int64_t(b0 + j) * ia.W] : 0.0;
+#pragma unroll
+      for (int j = 0; j < 32; ++j) part += v[j];
+    }
+    // exclusive prefix of the four partial sums (lanes 4g .. 4g+3 share a DPP row)
+    const int lane = int(threadIdx.x) & 63;
+    double incl = part, t = dpp_move<0x111>(incl);
+    incl = (lane & 3) >= 1 ? incl + t : incl;
+    t = dpp_move<0x112>(incl);
+    incl = (lane & 3) >= 2 ? incl + t : incl;
+    double acc = incl - part;
+    for (int b0 = bb; b0 < be; b0 += 32) {
+      double v[32];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) v[j] = (b0 + j < be) ? T[int64_t(b0 + j) * ia.W] : 0.0;
+#pragma unroll
+      for (int j = 0; j < 32; ++j)
+        if (b0 + j < be) {
+          T[int64_t(b0 + j) * ia.W] = acc;
+          acc += v[j];
+        }
+    }
+  } else if (i < ncol + int64_t(5) * ia.H) {
+    const int64_t k = i - ncol;
+    const int c = int(k / ia.H), y = int(k % ia.H);
+    double* T = L.RT + int64_t(c) * L.n_strips * ia.H + y;
+    double acc = 0.0;
+    for (int s0 = 0; s0 < L.n_strips; s0 += 16) {
+      double v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = (s0 + j < L.n_strips) ? T[int64_t(s0 + j) * ia.H] : 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (s0 + j < L.n_strips) {
+          T[int64_t(s0 + j) * ia.H] = acc;
+          acc += v[j];
+        }
+    }
+  }
+}
+
+// inclusive prefix of v over the workgroup's 256 threads (in thread order);
+// tot: LDS scratch of 4 x 5 doubles, free on entry and on return
+__device__ inline void block_scan5(double v[5], double (*tot)[5]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) v[c] = wave_scan_add(v[c]);
+  if (lane == 63)
+    for (int c = 0; c < 5; ++c) tot[wave][c] = v[c];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    double before = 0.0;
+    for (int w = 0; w < kIntWaves; ++w)
+      if (w < wave) before += tot[w][c];
+    v[c] += before;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void integral_final(IntegralArgs ia) {
+  __shared__ double red[2 * kIntWaves];
+  __shared__ double tot[kIntWaves][5];
+  __shared__ double wt[kIntBand][kIntWaves][5];  // per row: each wave's total (from the tiles pass)
+  __shared__ double rt[kIntBand][5];             // the strip's scanned row totals
+  const IntegralLayout L(ia);
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int s = int(blockIdx.x), b = int(blockIdx.y);
+  const int x = s * kBlock + tid, x0 = s * kBlock;
+  const int y0 = b * kIntBand, y1 = min(y0 + kIntBand, ia.H);
+  float z[kIntBand];
+  load_band(ia, x, y0, y1, z);
+  {
+    const double* src = L.tile_wt(s, b);
+    for (int i = tid; i < (y1 - y0) * kIntWaves * 5; i += kBlock) (&wt[0][0][0])[i] = src[i];
+    for (int i = tid; i < (y1 - y0) * 5; i += kBlock)
+      rt[i / 5][i % 5] = L.RT[(int64_t(i % 5) * L.n_strips + s) * ia.H + y0 + i / 5];
+  }
+  const double wref = integral_wref(ia, red);  // its barriers also publish wt and rt
+  if (s == 0 && b == 0 && tid == 0) ia.ws[0] = wref;
+  // the plane's zero first row (tiles of the first band) and first column
+  // (tiles of the first strip)
+  if (b == 0)
+    for (int c = 0; c < 5; ++c) {
+      if (x < ia.W) L.I[c * L.P + x + 1] = 0.0;
+      if (s == 0 && tid == 0) L.I[c * L.P] = 0.0;
+    }
+  if (s == 0)
+    for (int i = tid; i < (y1 - y0) * 5; i += kBlock)
+      L.I[(i % 5) * L.P + int64_t(y0 + i / 5 + 1) * L.ld] = 0.0;
+  // column carries: Pc[x] = sum_{x' <= x} Cb[x'] over the whole row (the part
+  // left of the strip, a strided sum reduced over the workgroup, plus the
+  // strip's own prefix)
+  double pc[5], left[5];
+  for (int c = 0; c < 5; ++c) {
+    const double* Cb = L.CT + (int64_t(c) * L.n_bands + b) * ia.W;
+    pc[c] = x < ia.W ? Cb[x] : 0.0;
+    double t = 0.0;
+    for (int xx = tid; xx < x0; xx += kBlock) t += Cb[xx];
+    left[c] = t;
+  }
+  block_scan5(pc, tot);
+  block_scan5(left, tot);  // thread 255 then holds the total of the strips to the left
+  if (tid == kBlock - 1)
+    for (int c = 0; c < 5; ++c) tot[0][c] = left[c];
+  __syncthreads();
+  for (int c = 0; c < 5; ++c) pc[c] += tot[0][c];
+  // rows: the strip's row prefix (wave scan plus the totals of the waves to
+  // the left), summed down the band, plus the carries
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, rc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < kIntBand; ++j) {
+    const int y = y0 + j;
+    if (y >= y1) break;
+    double v[5], r[5];
+    integrands(ia, x, y, z[j], wref, v);
+    const double yt = double(y - ia.H / 2);
+    wave_row_scan(v, yt, r);
+    for (int w = 0; w < kIntWaves; ++w)
+      if (w < wave)
+        for (int c = 0; c < 5; ++c)
+          if (c != 2) r[c] += wt[j][w][c];
+    r[2] = yt * r[0];
+    const int64_t row = int64_t(y + 1) * L.ld + x + 1;
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      double before = 0.0, all = 0.0;
-      for (int i = 0; i < kBlock / 64; ++i) {
-        if (i < wave) before += tot[i][c];
-        all += tot[i][c];
-      }
-      if (x < ia.W) I[c * P + int64_t(y + 1) * ld + x + 1] = carry[c] + before + v[c];
-      carry[c] += all;
-    }
-    __syncthreads();
-  }
-}
-
-// column totals of every band of kIntBand rows (rows 1 .. H of the planes)
-__global__ __launch_bounds__(kBlock) void integral_band_totals(IntegralArgs ia) {
-  const int x = int(blockIdx.x) * kBlock + threadIdx.x;
-  const int band = int(blockIdx.y);
-  if (x > ia.W) return;
-  const int64_t P = int_plane(ia), ld = ia.W + 1;
-  const int n_bands = (ia.H + kIntBand - 1) / kIntBand;
-  const double* I = ia.ws + kIntHeader;
-  double* T = ia.ws + kIntHeader + 5 * P;
-  const int y0 = 1 + band * kIntBand, y1 = min(y0 + kIntBand, ia.H + 1);
-  for (int c = 0; c < 5; ++c) {
-    double s = 0.0;
-    for (int yy = y0; yy < y1; ++yy) s += I[c * P + int64_t(yy) * ld + x];
-    T[(int64_t(c) * n_bands + band) * ld + x] = s;
-  }
-}
-
-// exclusive prefix of the band totals down each column (in place): one thread
-// per (column, channel), loads issued eight bands at a time
-__global__ __launch_bounds__(kBlock) void integral_band_scan(IntegralArgs ia) {
-  const int x = int(blockIdx.x) * kBlock + threadIdx.x;
-  const int c = int(blockIdx.y);
-  if (x > ia.W) return;
-  const int64_t P = int_plane(ia), ld = ia.W + 1;
-  const int n_bands = (ia.H + kIntBand - 1) / kIntBand;
-  double* T = ia.ws + kIntHeader + 5 * P + int64_t(c) * n_bands * ld;
-  double acc = 0.0;
-  for (int b0 = 0; b0 < n_bands; b0 += 8) {
-    double v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = (b0 + j < n_bands) ? T[int64_t(b0 + j) * ld + x] : 0.0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (b0 + j < n_bands) {
-        T[int64_t(b0 + j) * ld + x] = acc;
-        acc += v[j];
-      }
-  }
-}
-
-// column prefix sums within each band, started from the scanned totals of the bands above
-__global__ __launch_bounds__(kBlock) void integral_cols(IntegralArgs ia) {
-  const int x = int(blockIdx.x) * kBlock + threadIdx.x;
-  const int band = int(blockIdx.y);
-  if (x > ia.W) return;
-  const int64_t P = int_plane(ia), ld = ia.W + 1;
-  const int n_bands = (ia.H + kIntBand - 1) / kIntBand;
-  double* I = ia.ws + kIntHeader;
-  const double* T = ia.ws + kIntHeader + 5 * P;
-  const int y0 = 1 + band * kIntBand, y1 = min(y0 + kIntBand, ia.H + 1);
-  for (int c = 0; c < 5; ++c) {
-    double acc = T[(int64_t(c) * n_bands + band) * ld + x];
-    double v[kIntBand];
-#pragma unroll
-    for (int j = 0; j < kIntBand; ++j)
-      v[j] = (y0 + j < y1) ? I[c * P + int64_t(y0 + j) * ld + x] : 0.0;
-#pragma unroll
-    for (int j = 0; j < kIntBand; ++j) {
-      acc += v[j];
-      if (y0 + j < y1) I[c * P + int64_t(y0 + j) * ld + x] = acc;
+      rc[c] += rt[j][c];
+      acc[c] += r[c];
+      if (x < ia.W) L.I[c * L.P + row] = pc[c] + rc[c] + acc[c];
     }
   }
 }
@@ -2978,7 +3219,10 @@ size_t pf_integral_workspace_bytes(const pf_plan* plan) {
   if (!plan) return 0;
   const size_t ld = size_t(plan->W) + 1, P = (size_t(plan->H) + 1) * ld;
   const size_t bands = (size_t(plan->H) + kIntBand - 1) / kIntBand;
-  return sizeof(double) * (size_t(kIntHeader) + 5 * P + 5 * bands * ld);
+  const size_t strips = (size_t(plan->W) + kBlock - 1) / kBlock;
+  return sizeof(double) * (size_t(kIntHeader) + 5 * P + 5 * bands * size_t(plan->W) +
+                           5 * strips * size_t(plan->H) +
+                           bands * strips * size_t(kIntBand * kIntWaves * 5));
 }
 
 pf_status pf_integral_images(const pf_plan* plan, const float* depth, int64_t depth_pitch,
@@ -3002,13 +3246,13 @@ pf_status pf_integral_images(const pf_plan* plan, const float* depth, int64_t de
   ia.ws = static_cast<double*>(workspace);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const dim3 block(kBlock);
-  const unsigned strips = unsigned((plan->W + 1 + kBlock - 1) / kBlock);
+  const unsigned strips = unsigned((plan->W + kBlock - 1) / kBlock);
   const unsigned bands = unsigned((plan->H + kIntBand - 1) / kIntBand);
-  hipLaunchKernelGGL(integral_ref, dim3(1), block, 0, s, ia);
-  hipLaunchKernelGGL(integral_rows, dim3(unsigned(plan->H)), block, 0, s, ia);
-  hipLaunchKernelGGL(integral_band_totals, dim3(strips, bands), block, 0, s, ia);
-  hipLaunchKernelGGL(integral_band_scan, dim3(strips, 5), block, 0, s, ia);
-  hipLaunchKernelGGL(integral_cols, dim3(strips, bands), block, 0, s, ia);
+  const unsigned carry =
+      unsigned((5 * (int64_t(kCarryLanes) * plan->W + plan->H) + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(integral_tiles, dim3(strips, bands), block, 0, s, ia);
+  hipLaunchKernelGGL(integral_carry, dim3(carry), block, 0, s, ia);
+  hipLaunchKernelGGL(integral_final, dim3(strips, bands), block, 0, s, ia);
   const hipError_t err = hipGetLastError();
   if (err != hipSuccess) {
     g_last_hip_error = int(err);

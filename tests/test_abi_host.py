@@ -232,7 +232,10 @@ def test_rect_argument_checks_return_before_launch():
     code, plan = _create(H=48, W=64, k=5)
     assert code == 0
     need = lib.pf_integral_workspace_bytes(plan)
-    assert need == 8 * (32 + 5 * 49 * 65 + 5 * 3 * 65)
+    # header, five (H+1) x (W+1) planes, column totals of 3 bands of 16 rows,
+    # row totals of 1 strip of 256 columns, and the 4 waves' row totals of
+    # each of the 3 tiles
+    assert need == 8 * (32 + 5 * 49 * 65 + 5 * 3 * 64 + 5 * 1 * 48 + 3 * 1 * 16 * 4 * 5)
     fake = ctypes.c_void_p(0x10000)
     odd = ctypes.c_void_p(0x10004)
     assert lib.pf_integral_images(None, fake, 64, None, 0, fake, need, None) == 1

@@ -1,12 +1,16 @@
 """Host emulation of the fused kernel's output index map (no GPU): for the
 launch geometry a plan chooses, every output pixel is written by exactly one
-thread of one workgroup, and no store (scalar, float4 run or packed status
-word) touches a byte at or past the end of its plane.
+thread of one workgroup, no store (scalar, 16-byte group or packed status word)
+lands outside its plane, and the horizontal phase's LDS reads stay inside the
+column-sum rows.
 
 The emulation follows the kernel's own arithmetic: strip = wg % n_strips,
-band = wg / n_strips, rounds of ROWS rows, runs of RUN outputs per thread, and
-the vectorised run store taken only when the whole run lies in the strip and
-in the row."""
+band = wg / n_strips, rounds of ROWS rows, runs of RUN outputs per thread.
+Forward launches run every lane: a lane past the strip recomputes the strip's
+last run, and a store is kept only when its element offset, taken from the
+wave's first row of the round, lies in the wave's buffer range (its rows of
+the frame), which the hardware enforces by dropping the rest; the kernel sends
+a pixel outside the strip, the frame or the band a drop offset instead."""
 import numpy as np
 import pytest
 
@@ -28,12 +32,19 @@ def geometry(H, W, k, mode, shape=None, band_height=None):
     return tile_w, n_strips, tile_h, -(-H // tile_h), p.shape
 
 
+PITCH = 288                                    # LDS row pitch (columns) of the column sums
+SUB = {4: 72, 8: 36}                          # LDS layout (i % RUN) * SUB + i / RUN
+DROP = 0x80000000
+
+
 def emulate(H, W, k, mode, vec_store, shape=None, band_height=None):
-    """Bytes written per status position and per float position (one plane)."""
+    """Writes per output position (one plane; +64 positions to catch an overrun)."""
     tile_w, n_strips, tile_h, n_bands, shp = geometry(H, W, k, mode, shape, band_height)
     ROWS, RUN = SHAPES[shp]
+    lanes_per_row = BLOCK // RUN
+    rows_per_wave = 64 // lanes_per_row
     assert tile_w + k - 1 <= BLOCK
-    hits = np.zeros(H * W + 64, np.int32)        # +64: room to catch an overrun
+    hits = np.zeros(H * W + 64, np.int32)
     for wg in range(n_strips * n_bands):
         strip, band = wg % n_strips, wg // n_strips
         ox0 = strip * tile_w
@@ -42,20 +53,34 @@ def emulate(H, W, k, mode, vec_store, shape=None, band_height=None):
         for yg in range(yb, ye, ROWS):
             nr = min(ROWS, ye - yg)
             for tid in range(BLOCK):
-                hj, run = tid // (BLOCK // RUN), tid % (BLOCK // RUN)
-                o0 = run * RUN
-                o1 = min(o0 + RUN, tile_w)
-                if hj >= nr or o0 >= o1:
-                    continue
-                y0 = yg + hj
-                x0 = ox0 + o0
-                p = y0 * W + x0
-                if mode == "explicit" and vec_store and o0 + RUN <= o1 and x0 + RUN <= W:
-                    hits[p:p + RUN] += 1              # float4 runs and one status word
+                hj, run = tid // lanes_per_row, tid % lanes_per_row
+                h0 = (tid // 64 * 64) // lanes_per_row        # the wave's first row
+                o0s = run * RUN
+                o0 = min(o0s, (tile_w - 1) // RUN * RUN)      # the run this lane computes
+                # LDS reads: columns o0 .. o0 + RUN - 1 + k - 1 of row hj
+                i_max = o0 + RUN - 1 + k - 1
+                assert (RUN - 1) * SUB[RUN] + i_max // RUN < PITCH
+                base_row = min(yg + h0, H - 1)
+                rng = rows_per_wave * W                       # the wave's buffer range (elements)
+                cols = min(tile_w, W - ox0) if hj < nr else 0
+                base = (hj - h0) * W
+
+                def at(c):
+                    return base + c if c < cols else DROP
+
+                if mode == "explicit" and vec_store:
+                    for h in range(RUN // 4):
+                        e = at(o0s + 4 * h)
+                        if e != DROP:
+                            assert e % 4 == 0 and e + 4 <= rng
+                            g = base_row * W + ox0 + e
+                            hits[g:g + 4] += 1
                 else:
                     for q in range(RUN):
-                        if o0 + q < o1 and x0 + q < W:
-                            hits[p + q] += 1
+                        e = at(o0s + q)
+                        if e != DROP:
+                            assert e < rng
+                            hits[base_row * W + ox0 + e] += 1
     return hits
 
 

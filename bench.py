@@ -75,20 +75,22 @@ class Rig:
         self.pixels = H * W
 
 
-def time_launches(torch, pf, rig, intr, ks, mode, precision, steps, warmup):
+def time_launches(torch, pf, rig, intr, ks, mode, precision, steps, warmup, tuned=None):
     """One step = one launch fitting the frame at every k in ks (a batched launch
     when there are several).  The timed steps are replayed from captured HIP
     graphs, `chunk` consecutive steps (each on its own buffer set) per graph, so
     the kernels run back to back with no host gaps; HIP events on the replay
-    stream bracket every replay.  Returns (ms per step, ms per launch)."""
+    stream bracket every replay.  tuned = (band height, launch shape) of a
+    derived plan for a single-k step.  Returns (ms per step, ms per launch)."""
     H, W = rig.depth[0].shape
     for k in ks:
         pf.get_plan(intr, H, W, k, mode, precision)
+    bh, sh = tuned if tuned else (None, None)
 
     def run(s):
         if len(ks) == 1:
             pf.fit_planes(rig.depth[s], intr, ks[0], mode=mode, precision=precision,
-                          out=rig.outs[s][0])
+                          out=rig.outs[s][0], band_height=bh, shape=sh)
         else:
             pf.fit_planes_batch([rig.depth[s]] * len(ks), intr, list(ks), mode=mode,
                                 precision=precision, outs=rig.outs[s])
@@ -491,6 +493,11 @@ def cpu_baseline(frame, ks, mode, budget_s, threads=None):
                        f"k in {list(ks)}, {mode} mode, FP64, {total_t:.1f} s")
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -552,15 +559,24 @@ def main():
                      "avg_launch_ms": round(avg_launch_ms, 5)},
     }
     if not args.no_extras:
+        progress("headline done; extras")
         extras = {"copy_probe_256MiB": copy_probe}
         # per-window throughput of single-frame launches at 640x480: the
         # integral-image fit's cost per pixel should not grow with the window
-        per_k = {}
+        per_k, per_k_tuned = {}, {}
         for mode in ("implicit", "explicit"):
             for k in ks:
                 ms, avg = time_launches(torch, pf, rig, f.intrinsics, (k,), mode, "fp64", 64, 5)
                 per_k[f"{mode}_k{k}"] = round(rig.pixels / (ms * 1e-3) / 1e6, 1)
+                plan = pf.get_plan(f.intrinsics, 480, 640, k, mode, "fp64")
+                tuned = plan.autotune(rig.depth[0])
+                ms, avg = time_launches(torch, pf, rig, f.intrinsics, (k,), mode, "fp64", 64, 5,
+                                        tuned=tuned)
+                per_k_tuned[f"{mode}_k{k}"] = {"Mpx_s": round(rig.pixels / (ms * 1e-3) / 1e6, 1),
+                                               "band_rows": tuned[0], "shape": tuned[1]}
         extras["vga_single_frame_per_k_Mpx_s"] = per_k
+        extras["vga_single_frame_per_k_autotuned"] = per_k_tuned
+        progress("per-k done")
         for mode, prec in (("explicit", "fp64"), ("implicit", "fp32"), ("explicit", "fp32"),
                            ("implicit", "compensated"), ("explicit", "compensated")):
             ms, _ = time_launches(torch, pf, rig, f.intrinsics, ks, mode, prec, 64, 5)
@@ -587,6 +603,7 @@ def main():
         variants["disparity_implicit"] = {"ms_per_step": round(t, 5),
                                           "Mpx_s": round(rig.pixels * len(ks) / (t * 1e-3) / 1e6, 1)}
         extras["variants_vga_k3-15"] = variants
+        progress("variants done")
         del rig
         torch.cuda.empty_cache()
         hd = frames_for("hd_1920x1080")[0]
@@ -595,22 +612,41 @@ def main():
             for k in (15, 31):
                 ms, avg = time_launches(torch, pf, rig_hd, hd.intrinsics, (k,), mode, "fp64",
                                         40, 5)
-                extras[f"hd_{mode}_k{k}"] = {
+                rec = {"Mpx_s": round(rig_hd.pixels / (ms * 1e-3) / 1e6, 1),
+                       "avg_launch_ms": round(avg, 5),
+                       "hbm_frac": round(rig_hd.pixels * BYTES_PER_PIXEL / (avg * 1e-3) / 1e9 /
+                                         HBM_PEAK_GBS, 4)}
+                # the band height and launch shape pf_plan_autotune picks on this frame
+                plan = pf.get_plan(hd.intrinsics, 1080, 1920, k, mode, "fp64")
+                tuned = plan.autotune(rig_hd.depth[0])
+                ms, avg = time_launches(torch, pf, rig_hd, hd.intrinsics, (k,), mode, "fp64",
+                                        40, 5, tuned=tuned)
+                rec["autotuned"] = {
+                    "band_rows": tuned[0], "shape": tuned[1],
                     "Mpx_s": round(rig_hd.pixels / (ms * 1e-3) / 1e6, 1),
                     "avg_launch_ms": round(avg, 5),
                     "hbm_frac": round(rig_hd.pixels * BYTES_PER_PIXEL / (avg * 1e-3) / 1e9 /
                                       HBM_PEAK_GBS, 4)}
+                extras[f"hd_{mode}_k{k}"] = rec
+        for mode in ("implicit", "explicit"):
+            t15 = extras[f"hd_{mode}_k15"]["autotuned"]["Mpx_s"]
+            t31 = extras[f"hd_{mode}_k31"]["autotuned"]["Mpx_s"]
+            # the integral-image fit's cost per pixel should not grow with the window
+            extras[f"hd_{mode}_k31_over_k15_autotuned"] = round(t31 / t15, 3)
         del rig_hd
         torch.cuda.empty_cache()
+        progress("1080p done")
         extras["batch_mixed_64"] = batch_measure(torch, pf, np, frames_for)
         extras["batch_mixed_64_queued"] = batch_measure(torch, pf, np, frames_for, queued=True)
         extras["latency_160x120"] = latency_measure(torch, pf, frames_for)
+        progress("batches and latency done")
         extras["diff_8x640x480"] = diff_measure(torch, pf, np, frames_for, diff_loss_inputs)
         extras["xyz_vs_rgbd"] = xyz_measure(torch, pf, frames_for)
         extras["rects_1080p"] = rects_measure(torch, pf, np, frames_for)
         extras["autotune_vga_k9"] = autotune_measure(torch, pf, frames_for)
         out["extras"] = extras
     if not args.no_cpu_baseline:
+        progress("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(f, ks, "implicit", args.cpu_seconds)
         one = cpu_baseline(f, ks, "implicit", max(2.0, args.cpu_seconds / 4), threads=1)
         out["cpu_baseline"]["one_thread"] = {"value": one["value"], "sample": one["sample"]}

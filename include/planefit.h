@@ -175,9 +175,11 @@ int32_t pf_plan_band_height(const pf_plan* plan);
  * tiling at two workgroups per compute unit (twice the registers); 2 = rounds
  * of 8 rows and runs of 8 outputs per thread at two workgroups per compute
  * unit.  Shapes 1 and 2 apply to PF_PREC_FP64 implicit and explicit
- * full-window plans; every other plan runs shape 0.  Results do not depend on
- * the shape beyond the accuracy of the path (the band height moves which pixels
- * share a reference disparity). */
+ * full-window plans; every other plan runs shape 0.  A new plan runs shape 1
+ * when it is a PF_PREC_FP64 full-window PF_IMPLICIT plan and shape 0
+ * otherwise.  Shapes 0 and 1 give bit-identical results at the same band
+ * height; otherwise results do not depend on the shape beyond the accuracy of
+ * the path (the band height moves which pixels share a reference disparity). */
 int32_t pf_plan_shape(const pf_plan* plan);  /* -1 for NULL */
 
 /* A new plan equal to `plan` except for its launch shape: `band_height` output

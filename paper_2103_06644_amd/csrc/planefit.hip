@@ -2464,17 +2464,16 @@ struct pf_plan {
 
 namespace {
 // The default band height of a plan for launch shape `shape`: enough
-// workgroups for one full round of the chip (its workgroups per CU on 256 CUs),
-// with at least 8 rows for the explicit solve, whose per-band warm-up and
-// prologue would otherwise outweigh its short per-pixel work.  Rounded up to
-// whole rounds of rows: a band of 4q + 1 rows costs as many rounds as one of
-// 4q + 4, whose fewer workgroups then share the chip (1920x1080, k = 15:
-// 9 -> 12 rows, +10 % implicit, +4 % explicit).
+// workgroups for one full round of the chip at four workgroups per CU (two for
+// the 8 x 8 shape) on 256 CUs, whatever the shape's occupancy, and at least one
+// round of rows.  Rounded up to whole rounds of rows: a band of 4q + 1 rows
+// costs as many rounds as one of 4q + 4, whose fewer workgroups then share the
+// chip (1920x1080, k = 15: 9 -> 12 rows).
 int64_t default_band_height(const pf_plan* p, int shape) {
-  const int64_t target_groups = 256 * int64_t(shape_groups(shape));
+  const int64_t target_groups = shape_rows(shape) == 4 ? 1024 : 256 * int64_t(shape_groups(shape));
   const int64_t round_rows = shape_rows(shape);
   int64_t th = (p->H * p->n_strips + target_groups - 1) / target_groups;
-  th = std::max<int64_t>(th, p->params.mode == PF_EXPLICIT ? 8 : 4);
+  th = std::max<int64_t>(th, 4);
   th = (th + round_rows - 1) / round_rows * round_rows;
   return std::min<int64_t>(th, p->H);
 }
@@ -2542,10 +2541,11 @@ pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t widt
   const int tw_max = ((kBlock - (k - 1)) / 4) * 4;
   p->n_strips = int((width + tw_max - 1) / tw_max);
   p->tile_w = int(((width + p->n_strips - 1) / p->n_strips + 3) / 4 * 4);
-  // launch shape: FP64 explicit keeps its run's outputs in registers, which
-  // two workgroups per CU hold without spilling (measured +9 % at 1920x1080,
-  // k = 15); everything else runs four workgroups per CU
-  p->shape = (p->shapes_allowed() && params->mode == PF_EXPLICIT) ? 1 : 0;
+  // launch shape: the FP64 implicit fit runs two workgroups per CU, with room
+  // for 256 registers per lane (same tiles and results as four per CU; measured
+  // 30.3 against 32.4 us on the 640x480 frame at k = 3, 5, 9, 15 in one launch,
+  // 47.1 against 48.9 us at 1920x1080, k = 15); everything else runs four
+  p->shape = (p->shapes_allowed() && params->mode == PF_IMPLICIT) ? 1 : 0;
   int64_t th = default_band_height(p, p->shape);
   // tuning override of the band height (rows of output per workgroup)
   if (const char* env = std::getenv("PF_TILE_H")) {

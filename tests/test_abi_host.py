@@ -283,21 +283,24 @@ def test_autotune_argument_checks_return_before_launch():
 
 @pytest.mark.parametrize("H,W,k,mode,rows", [
     (480, 640, 9, "implicit", 4),      # 3 strips x 480 rows fit one round at the 4-row minimum
-    (480, 640, 9, "explicit", 8),      # the explicit minimum
+    (480, 640, 9, "explicit", 4),      # the 4-row minimum
     (1080, 1920, 15, "implicit", 12),  # 8 strips: 9 rows for one round, rounded up to whole 4-row rounds
-    (1080, 1920, 15, "explicit", 20),  # two workgroups per CU: 17 rows for 512 -> 20
+    (1080, 1920, 15, "explicit", 12),  # 9 rows -> 12
+    (1080, 1920, 31, "explicit", 12),
     (1080, 1920, 31, "implicit", 12),  # 9 strips: 10 rows -> 12
     (720, 1280, 5, "implicit", 8),     # 6 strips: 5 rows -> 8
     (30, 40, 3, "implicit", 4),
-    (6, 40, 3, "explicit", 6),         # never taller than the frame
+    (6, 40, 3, "explicit", 4),
+    (3, 40, 3, "explicit", 3),         # never taller than the frame
 ])
 def test_default_band_height_is_whole_rounds(H, W, k, mode, rows):
-    """The plan's band height: one round of the chip's workgroup slots (1,024 at
-    four per CU; 512 for the FP64 explicit shape at two per CU), at least 4 rows
-    (implicit) or 8 (explicit), rounded up to a multiple of the kernel's 4-row
-    round and capped at the frame height."""
+    """The plan's band height: one round of 1,024 workgroups (four per CU on 256
+    CUs, whatever the launch shape's occupancy), at least 4 rows, rounded up to a
+    multiple of the kernel's 4-row round and capped at the frame height.  The default launch shape is two workgroups per CU for
+    the FP64 implicit fit and four otherwise."""
     p = pf.Plan((525.0, 525.0, W / 2 - 0.5, H / 2 - 0.5), H, W, k, mode)
     assert p.tile_h == rows
+    assert p.shape == (1 if mode == "implicit" else 0)
 
 
 def test_derive_leaves_the_plan_alone():
@@ -311,11 +314,11 @@ def test_derive_leaves_the_plan_alone():
     assert lib.pf_plan_derive(plan, 12, -1, ctypes.byref(out)) == 0
     assert lib.pf_plan_band_height(out) == 12
     assert lib.pf_plan_band_height(plan) == before
-    assert lib.pf_plan_shape(out) == lib.pf_plan_shape(plan) == 0
+    assert lib.pf_plan_shape(out) == lib.pf_plan_shape(plan) == 1   # FP64 implicit default
     big = ctypes.c_void_p()
     assert lib.pf_plan_derive(plan, 100000, 2, ctypes.byref(big)) == 0
     assert lib.pf_plan_band_height(big) == 480              # clamped to the frame
-    assert lib.pf_plan_shape(big) == 2 and lib.pf_plan_shape(plan) == 0
+    assert lib.pf_plan_shape(big) == 2 and lib.pf_plan_shape(plan) == 1
     rule = ctypes.c_void_p()
     assert lib.pf_plan_derive(plan, 0, 1, ctypes.byref(rule)) == 0   # the shape's own rule
     assert lib.pf_plan_band_height(rule) >= 4
@@ -328,7 +331,7 @@ def test_derive_leaves_the_plan_alone():
     code, p32 = _create(H=480, W=640, k=9, prec=1)
     assert lib.pf_plan_derive(p32, 8, 2, ctypes.byref(bad)) == 8
     code, pex = _create(H=480, W=640, k=9, mode=1)
-    assert lib.pf_plan_shape(pex) == 1                      # FP64 explicit default
+    assert lib.pf_plan_shape(pex) == 0                      # FP64 explicit default
     for h in (out, big, rule, plan, p32, pex):
         lib.pf_plan_destroy(h)
 

@@ -64,3 +64,25 @@ def test_every_shape_at_parity(gpu, mode, shape, bh):
                                 shape=shape)[0]
     for x, y in zip((n, o_, r, s), batch):
         assert torch.equal(torch.nan_to_num(x.float(), 7.0), torch.nan_to_num(y.float(), 7.0))
+
+
+@pytest.mark.parametrize("mode", ["implicit", "explicit"])
+def test_shapes_zero_and_one_bit_identical(gpu, mode):
+    """Launch shapes 0 and 1 share their tiling (4 x 4) and differ only in
+    workgroups per CU, so at one band height their outputs are equal bit for
+    bit, and the default plan (shape 1 for implicit, 0 for explicit) equals
+    the other shape at its own band height."""
+    import torch
+    import paper_2103_06644_amd as pf
+    f = frames_for("vga_640x480")[0]
+    d = torch.from_numpy(f.depth).cuda()
+    plan = pf.get_plan(f.intrinsics, 480, 640, 9, mode, "fp64")
+    assert plan.shape == (1 if mode == "implicit" else 0)
+    outs = {}
+    for sh in (0, 1):
+        outs[sh] = pf.fit_planes(d, f.intrinsics, 9, mode=mode, band_height=plan.tile_h, shape=sh)
+    default = pf.fit_planes(d, f.intrinsics, 9, mode=mode)
+    torch.cuda.synchronize()
+    for a, b, c in zip(outs[0], outs[1], default):
+        assert torch.equal(torch.nan_to_num(a.float(), 7.0), torch.nan_to_num(b.float(), 7.0))
+        assert torch.equal(torch.nan_to_num(a.float(), 7.0), torch.nan_to_num(c.float(), 7.0))

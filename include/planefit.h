@@ -171,10 +171,10 @@ pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_p
 int32_t pf_plan_band_height(const pf_plan* plan);
 
 /* Launch shapes (tiling of the fused kernel): 0 = rounds of 4 rows and runs of
- * 4 outputs per thread at four workgroups per compute unit; 1 = the same
- * tiling at two workgroups per compute unit (twice the registers); 2 = rounds
- * of 8 rows and runs of 8 outputs per thread at two workgroups per compute
- * unit.  Shapes 1 and 2 apply to PF_PREC_FP64 implicit and explicit
+ * 4 outputs per thread, compiled for four workgroups per compute unit; 1 =
+ * the same tiling compiled for two (twice the registers; a kernel that still
+ * fits four runs four); 2 = rounds of 8 rows and runs of 8 outputs per thread
+ * at two workgroups per compute unit.  Shapes 1 and 2 apply to PF_PREC_FP64 implicit and explicit
  * full-window plans; every other plan runs shape 0.  A new plan runs shape 1
  * when it is a PF_PREC_FP64 full-window PF_IMPLICIT plan and shape 0
  * otherwise.  Shapes 0 and 1 give bit-identical results at the same band

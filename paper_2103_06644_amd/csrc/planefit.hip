@@ -59,9 +59,12 @@ constexpr int kMaxWindow = 63;
 // outputs of one row (kBlock / run runs per row, rows * kBlock / run = kBlock
 // threads); `groups` is the number of workgroups per CU the register budget
 // is sized for (four: 128 VGPRs; two: 256).
-//   shape 0: 4 x 4, four workgroups per CU (32 KB of LDS in FP64);
-//   shape 1: 4 x 4, two workgroups per CU (the FP64 explicit solve keeps its
-//            four outputs' stores in registers without spilling);
+//   shape 0: 4 x 4, register budget of four workgroups per CU (128 VGPRs;
+//            32 KB of LDS in FP64);
+//   shape 1: 4 x 4, budget of two workgroups per CU (256 VGPRs).  The FP64
+//            implicit kernel still fits in 127, so it runs four per CU like
+//            shape 0, with the schedule the larger budget allows (the default
+//            for FP64 implicit fits, measured faster);
 //   shape 2: 8 x 8, two workgroups per CU (64 KB of LDS; half the per-run
 //            warm-up and half the barriers per row).
 // Shapes 1 and 2 exist for FP64 implicit and explicit full-window fits (the
@@ -2541,10 +2544,11 @@ pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t widt
   const int tw_max = ((kBlock - (k - 1)) / 4) * 4;
   p->n_strips = int((width + tw_max - 1) / tw_max);
   p->tile_w = int(((width + p->n_strips - 1) / p->n_strips + 3) / 4 * 4);
-  // launch shape: the FP64 implicit fit runs two workgroups per CU, with room
-  // for 256 registers per lane (same tiles and results as four per CU; measured
-  // 30.3 against 32.4 us on the 640x480 frame at k = 3, 5, 9, 15 in one launch,
-  // 47.1 against 48.9 us at 1920x1080, k = 15); everything else runs four
+  // launch shape: the FP64 implicit fit is compiled for a budget of two
+  // workgroups per CU (same tiles and results as shape 0, and it still fits
+  // four per CU; measured 30.3 against 32.4 us on the 640x480 frame at
+  // k = 3, 5, 9, 15 in one launch, 47.1 against 48.9 us at 1920x1080, k = 15);
+  // everything else runs shape 0
   p->shape = (p->shapes_allowed() && params->mode == PF_IMPLICIT) ? 1 : 0;
   int64_t th = default_band_height(p, p->shape);
   // tuning override of the band height (rows of output per workgroup)

@@ -346,7 +346,7 @@ pf_status pf_fit_planes_xyz(const pf_plan* plan, const float* depth, int64_t dep
  * pf_integral_images builds, in FP64 on the GPU, the integral images of the
  * four depth-dependent moments of Eq. 14 (centred on the frame's reference
  * disparity) and of the valid count into the caller's workspace (three
- * launches over tiles of 256 columns by 32 rows: tile totals, their scans,
+ * launches over tiles of 256 columns by 16 rows: tile totals, their scans,
  * then each tile's own prefix plus its carries; the depth is read twice and
  * each image entry written once).  pf_fit_rects then fits one plane per rectangle from the four
  * corners of each image; the camera-only moments of a w x h rectangle are in

@@ -245,7 +245,9 @@ size_t pf_batch_workspace_bytes(int32_t n);
  * nodes only and every replay starts from a fresh queue.  Arguments, checks,
  * plan compatibility and results are those of pf_fit_planes_batch (bit for bit
  * the same outputs).  Up to 32 frames fit in one launch's arguments: such a
- * batch is that single launch (the workspace is then not used).
+ * batch is that single launch (the workspace is then not used).  With the
+ * environment variable PF_QUEUE_DEBUG set, each persistent launch prints its
+ * grid (workgroups per CU x CUs, work items) to stderr.
  *   workspace  device, >= pf_batch_workspace_bytes(n), 256-byte aligned
  *              (else PF_ERR_WORKSPACE); owned by the caller, rewritten by every
  *              call: calls that overlap in time need separate workspaces. */

@@ -1340,7 +1340,10 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
 
   for (int yg = yb; yg < ye; yg += TL::rows) {
     const int nr = min(TL::rows, ye - yg);
-    // vertical phase: window column sums for nr output rows
+    // vertical phase: window column sums for nr output rows.  Rows of the
+    // round past the band get empty sums: forward launches run their
+    // horizontal phase too (see below), which then sees all-invalid windows
+    // rather than stale or never-written LDS.
 #pragma unroll
     for (int j = 0; j < TL::rows; ++j) {
       if (j < nr) {
@@ -1354,6 +1357,15 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
         if (PARTIAL) {
           syn[j * kPitch + li] = col.yn;
           sy2n[j * kPitch + li] = col.y2n;
+        }
+      } else if (!BWD) {
+        sw[j * kPitch + li] = T(0);
+        syw[j * kPitch + li] = T(0);
+        sww[j * kPitch + li] = T(0);
+        sn[j * kPitch + li] = 0;
+        if (PARTIAL) {
+          syn[j * kPitch + li] = 0;
+          sy2n[j * kPitch + li] = 0;
         }
       }
     }
@@ -2550,12 +2562,7 @@ pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t widt
   // k = 3, 5, 9, 15 in one launch, 47.1 against 48.9 us at 1920x1080, k = 15);
   // everything else runs shape 0
   p->shape = (p->shapes_allowed() && params->mode == PF_IMPLICIT) ? 1 : 0;
-  int64_t th = default_band_height(p, p->shape);
-  // tuning override of the band height (rows of output per workgroup)
-  if (const char* env = std::getenv("PF_TILE_H")) {
-    const long v = std::strtol(env, nullptr, 10);
-    if (v >= 1) th = std::min<int64_t>(v, height);
-  }
+  const int64_t th = default_band_height(p, p->shape);  // pf_plan_derive sets others
   p->tile_h = int(th);
   p->n_bands = int((height + th - 1) / th);
   *out = p;

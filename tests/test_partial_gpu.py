@@ -95,3 +95,26 @@ def test_partial_collinear_batch_and_full_rule(gpu):
             for x, y in zip(batch[i], single):
                 assert torch.equal(torch.nan_to_num(x.float(), 7.0),
                                    torch.nan_to_num(y.float(), 7.0)), (mode, k)
+
+
+@pytest.mark.parametrize("mode", ["implicit", "explicit"])
+@pytest.mark.parametrize("H,band", [(3, None), (5, None), (6, 6), (13, 5)])
+def test_partial_bands_shorter_than_a_round(gpu, mode, H, band):
+    """Bands whose last round has fewer rows than the kernel's 4-row round:
+    the idle rows of that round run the horizontal phase on empty column sums
+    and store nothing.  Every output pixel still equals the oracle's fit (a
+    40-column crop with holes, k = 3, min_valid = 5)."""
+    import torch
+    import paper_2103_06644_amd as pf
+    f = frames_for("vga_640x480")[0]
+    z = np.ascontiguousarray(f.depth[200:200 + H, 300:340])
+    fx, fy, cx, cy = f.intrinsics
+    intr = (fx, fy, cx - 300, cy - 200)
+    print("[case] partial short bands", mode, H, band, flush=True)
+    d = torch.from_numpy(z).cuda()
+    n, o_, r, s = pf.fit_planes(d, intr, 3, mode=mode, min_valid=5, band_height=band)
+    torch.cuda.synchronize()
+    g = dict(normals=n.cpu().numpy().astype(np.float64), offsets=o_.cpu().numpy().astype(np.float64),
+             residuals=r.cpu().numpy().astype(np.float64), status=s.cpu().numpy())
+    o = oracle.fit_planes(z.astype(np.float64), intr, 3, mode, min_valid=5)
+    PT.assert_parity(PT.check(g, o, mode, z, intr))

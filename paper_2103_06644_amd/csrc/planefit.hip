@@ -1235,10 +1235,15 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
   a.dscale = lc.dscale;
   a.min_valid = job.min_valid;
 
+  // Implicit forward fits with runs of four pack each wave's valid windows
+  // before solving them (below); the count rows are then twice as long, so
+  // that a wave's four rows hold its 256 packed windows.
+  constexpr bool PACK = MODE != PF_EXPLICIT && !BWD && !PARTIAL && TL::run == 4;
+  constexpr int kNPitch = PACK ? 2 * kPitch : kPitch;
   __shared__ T sw[TL::rows * kPitch];
   __shared__ T syw[TL::rows * kPitch];
   __shared__ T sww[TL::rows * kPitch];
-  __shared__ int sn[TL::rows * kPitch];
+  __shared__ __align__(16) int sn[TL::rows * kNPitch];
   __shared__ int syn[PARTIAL ? TL::rows * kPitch : 1];   // partial windows: sum y~ per column
   __shared__ int sy2n[PARTIAL ? TL::rows * kPitch : 1];  // and sum y~^2
   __shared__ double red[2 * (kBlock / 64)];
@@ -1328,7 +1333,10 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
   }
 
   const int li = lds_index<SHAPE>(tid);
-  const int hj = tid / (kBlock / TL::run);      // row of the round this thread fits in the horizontal phase
+  // row of the round this thread fits in the horizontal phase (runs of four:
+  // one row per wave, so a wave-uniform value)
+  const int hj = TL::run == 4 ? __builtin_amdgcn_readfirstlane(tid / (kBlock / TL::run))
+                              : tid / (kBlock / TL::run);
   const int run = tid % (kBlock / TL::run);
   const int o0s = run * TL::run;   // first output column (strip-relative) of the run
   // Forward launches run the horizontal phase on every lane: a lane whose run
@@ -1353,7 +1361,7 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
         sw[j * kPitch + li] = col.w;
         syw[j * kPitch + li] = col.yw;
         sww[j * kPitch + li] = col.ww;
-        sn[j * kPitch + li] = col.n;
+        sn[j * kNPitch + li] = col.n;
         if (PARTIAL) {
           syn[j * kPitch + li] = col.yn;
           sy2n[j * kPitch + li] = col.y2n;
@@ -1362,7 +1370,7 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
         sw[j * kPitch + li] = T(0);
         syw[j * kPitch + li] = T(0);
         sww[j * kPitch + li] = T(0);
-        sn[j * kPitch + li] = 0;
+        sn[j * kNPitch + li] = 0;
         if (PARTIAL) {
           syn[j * kPitch + li] = 0;
           sy2n[j * kPitch + li] = 0;
@@ -1388,7 +1396,7 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
       const T* rw = sw + hj * kPitch;
       const T* ryw = syw + hj * kPitch;
       const T* rww = sww + hj * kPitch;
-      const int* rn = sn + hj * kPitch;
+      const int* rn = sn + hj * kNPitch;
       const int base = o0 + a.r;  // x - x_c = (i - base) - (o - o0)
       // window sums slid along the run: column o + k - 1 enters as column o leaves
       T hw = T(0), hx = T(0), hy = T(0), hww = T(0);
@@ -1508,7 +1516,90 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
         // later and does not wait for them to complete.
         int cols;
         const RowOut<TL::run / 4> ro(a, yg, hj, nr, ox0, cols);
-        if constexpr (MODE != PF_EXPLICIT) {
+        if constexpr (PACK) {
+          // A wave fits one row: 64 lanes x 4 windows.  Solving them lane by
+          // lane costs a full solve round per window of the run whenever any
+          // lane's window is valid, and near holes most are not.  So the sums
+          // of all four windows are taken first; then the wave packs its valid
+          // windows into consecutive slots of its own LDS rows (only this wave
+          // reads them, and it has read them all: LDS serves a wave's accesses
+          // in order), the other in-frame pixels after them, and solves 64
+          // slots at a time.  Results are those of the per-lane solve, bit for
+          // bit.
+          T pB[4], pX[4], pY[4], pQ[4];
+          bool keep[4], fit[4];
+          // the run's columns, opaque to the compiler: the LDS addresses of
+          // the four steps are then formed here in each round rather than
+          // hoisted out of the round loop, where they would hold registers
+          // across the solve
+          int ob = o0;
+          __asm__ volatile("" : "+v"(ob));
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int o = ob + q;
+            enter(o + a.k - 1);
+            pB[q] = hw;
+            pQ[q] = hww;
+            pX[q] = hx - T(q) * hw;
+            pY[q] = hy - T(y0 - y_ref) * hw;
+            keep[q] = o0s + q < cols;
+            fit[q] = keep[q] && hn == a.k * a.k;
+            leave(o);
+          }
+          uint64_t mfit[4], mrest[4];
+          int nfit = 0, nrest = 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            mfit[q] = __builtin_amdgcn_ballot_w64(fit[q]);
+            mrest[q] = __builtin_amdgcn_ballot_w64(keep[q] && !fit[q]);
+            nfit += __builtin_popcountll(mfit[q]);
+            nrest += __builtin_popcountll(mrest[q]);
+          }
+          T* kB = sw + hj * kPitch;
+          T* kX = syw + hj * kPitch;
+          T* kY = sww + hj * kPitch;
+          T* kQ = reinterpret_cast<T*>(sn + hj * kNPitch);
+          uint8_t* kc = reinterpret_cast<uint8_t*>(kQ + kBlock);
+          static_assert(kBlock * sizeof(T) + kBlock <= kNPitch * sizeof(int), "packed row");
+          __asm__ volatile("" ::: "memory");  // every read of the column sums comes first
+          int sf = 0, sr = nfit;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const uint64_t mf = mfit[q], mr = mrest[q];
+            const int bf = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mf >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo(uint32_t(mf), 0u)));
+            const int br = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mr >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo(uint32_t(mr), 0u)));
+            if (fit[q]) {
+              const int s = sf + bf;
+              kB[s] = pB[q];
+              kX[s] = pX[q];
+              kY[s] = pY[q];
+              kQ[s] = pQ[q];
+              kc[s] = uint8_t(o0s + q);
+            } else if (keep[q]) {
+              kc[sr + br] = uint8_t(o0s + q);
+            }
+            sf += __builtin_popcountll(mf);
+            sr += __builtin_popcountll(mr);
+          }
+          __asm__ volatile("" ::: "memory");
+          const int lane = tid & 63;
+          const int n = nfit + nrest;
+#pragma unroll 1
+          for (int s0 = 0; s0 < n; s0 += 64) {
+            const int s = s0 + lane;
+            const int c = s < n ? int(kc[s]) : 0;
+            PixelOut po = invalid_pixel();
+            if (s < nfit) {
+              if constexpr (std::is_same<T, df32>::value)
+                po = solve_pixel_df<MODE>(a, kB[s], kX[s], kY[s], kQ[s], a.k * a.k, w_ref, ox0 + c, y0);
+              else
+                po = solve_pixel<T, MODE>(a, kB[s], kX[s], kY[s], kQ[s], a.k * a.k, w_ref, ox0 + c, y0);
+            }
+            ro.put(s < n ? ro.at(c, cols) : kDropOffset, po);
+          }
+        } else if constexpr (MODE != PF_EXPLICIT) {
           // one pixel at a time, each stored as soon as it is solved (the
           // eigen-solve is large: the loop stays rolled)
 #pragma unroll 1

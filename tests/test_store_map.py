@@ -10,7 +10,14 @@ Forward launches run every lane: a lane past the strip recomputes the strip's
 last run, and a store is kept only when its element offset, taken from the
 wave's first row of the round, lies in the wave's buffer range (its rows of
 the frame), which the hardware enforces by dropping the rest; the kernel sends
-a pixel outside the strip, the frame or the band a drop offset instead."""
+a pixel outside the strip, the frame or the band a drop offset instead.
+
+Implicit fits with runs of four pack each wave's windows before solving: the
+windows with a full valid count take slots 0 .. nfit-1 in (window of the run,
+lane) order, the other in-frame pixels the slots after them, each slot keeping
+its column; slot s is then solved and stored by lane s % 64 in round s / 64.
+Which windows are valid depends on the depth, so the emulation draws it at
+random."""
 import numpy as np
 import pytest
 
@@ -37,7 +44,44 @@ SUB = {4: 72, 8: 36}                          # LDS layout (i % RUN) * SUB + i /
 DROP = 0x80000000
 
 
-def emulate(H, W, k, mode, vec_store, shape=None, band_height=None):
+KPITCH_N = 2 * PITCH                           # count-row pitch (ints) when windows are packed
+
+
+def emulate_packed(hits, W, ox0, tile_w, yg, nr, rng, p_fit):
+    """One round of the packed implicit store path (runs of four: wave = row)."""
+    for hj in range(4):
+        cols = min(tile_w, W - ox0) if hj < nr else 0
+        keep = 4 * np.arange(64)[None, :] + np.arange(4)[:, None] < cols
+        fit = keep & (rng.random((4, 64)) < p_fit)
+        nfit, nrest = int(fit.sum()), int((keep & ~fit).sum())
+        n = nfit + nrest
+        assert n <= BLOCK
+        # the packed row: 256 doubles then 256 column bytes inside the count row
+        assert BLOCK * 8 + BLOCK <= KPITCH_N * 4
+        col = np.full(BLOCK, -1)
+        sf, sr = 0, nfit
+        lanes = np.arange(64)
+        for q in range(4):
+            rest = keep[q] & ~fit[q]
+            # mbcnt: set bits of the wave's ballot below each lane
+            for mask, start in ((fit[q], sf), (rest, sr)):
+                below = np.cumsum(mask) - mask
+                slots = start + below[mask]
+                assert (col[slots] == -1).all()
+                col[slots] = 4 * lanes[mask] + q
+            assert (col[sf:sf + fit[q].sum()] >= 0).all()
+            sf += int(fit[q].sum())
+            sr += int(rest.sum())
+        assert sf == nfit and sr == n
+        assert (col[:n] >= 0).all() and (col[n:] == -1).all()
+        assert (col[:n] < 256).all()                          # kept in one byte
+        # round s // 64, lane s % 64 stores slot s: every slot below n, once
+        c = col[:n]
+        assert (c < cols).all()
+        np.add.at(hits, (yg + hj) * W + ox0 + c, 1)
+
+
+def emulate(H, W, k, mode, vec_store, shape=None, band_height=None, p_fit=None, seed=0):
     """Writes per output position (one plane; +64 positions to catch an overrun)."""
     tile_w, n_strips, tile_h, n_bands, shp = geometry(H, W, k, mode, shape, band_height)
     ROWS, RUN = SHAPES[shp]
@@ -45,6 +89,8 @@ def emulate(H, W, k, mode, vec_store, shape=None, band_height=None):
     rows_per_wave = 64 // lanes_per_row
     assert tile_w + k - 1 <= BLOCK
     hits = np.zeros(H * W + 64, np.int32)
+    packed = mode == "implicit" and RUN == 4
+    rng = np.random.default_rng(seed)
     for wg in range(n_strips * n_bands):
         strip, band = wg % n_strips, wg // n_strips
         ox0 = strip * tile_w
@@ -52,6 +98,9 @@ def emulate(H, W, k, mode, vec_store, shape=None, band_height=None):
         ye = min(yb + tile_h, H)
         for yg in range(yb, ye, ROWS):
             nr = min(ROWS, ye - yg)
+            if packed:
+                emulate_packed(hits, W, ox0, tile_w, yg, nr, rng, 0.6 if p_fit is None else p_fit)
+                continue
             for tid in range(BLOCK):
                 hj, run = tid // lanes_per_row, tid % lanes_per_row
                 h0 = (tid // 64 * 64) // lanes_per_row        # the wave's first row
@@ -105,3 +154,14 @@ def test_every_shape_writes_each_pixel_once(H, W, k, mode, shape, bh):
     hits = emulate(H, W, k, mode, vec, shape, bh)
     assert np.all(hits[:H * W] == 1), np.unique(hits[:H * W], return_counts=True)
     assert not hits[H * W:].any()
+
+
+@pytest.mark.parametrize("p_fit", [0.0, 0.3, 1.0])
+@pytest.mark.parametrize("H,W,k", [(37, 93, 7), (120, 160, 5), (63, 63, 63)])
+def test_packed_implicit_writes_each_pixel_once(H, W, k, p_fit):
+    """Any pattern of valid windows (none, some, all): every in-frame pixel is
+    stored once, from its own slot, and nothing else is."""
+    for shape, bh in ((0, None), (1, 6), (0, 5)):
+        hits = emulate(H, W, k, "implicit", W % 4 == 0, shape, bh, p_fit=p_fit, seed=k)
+        assert np.all(hits[:H * W] == 1), np.unique(hits[:H * W], return_counts=True)
+        assert not hits[H * W:].any()

@@ -227,9 +227,32 @@ typedef struct {
  * the launch shape, and be all partial-window plans or all full-window ones
  * (else PF_ERR_UNSUPPORTED); partial-window plans may differ in min_valid.  Every
  * frame is checked on the host as in pf_fit_planes before anything is
- * enqueued; n = 0 is a no-op.  No workspace is needed. */
+ * enqueued; n = 0 is a no-op.  No workspace is needed.
+ * Band heights are planned for the whole batch (pf_batch_band_heights): a plan
+ * whose band height is the default rule's may run taller bands in a batch that
+ * holds more workgroups than the chip keeps resident.  A frame's outputs depend
+ * on its band height at the rounding level only (well inside the parity bar);
+ * fitted alone with the height pf_batch_band_heights reports for it (or with a
+ * plan whose height is set, pf_plan_derive), it comes out bit for bit the same
+ * as in the batch.  Frames within a launch start in order of decreasing window
+ * size, which does not affect results. */
 pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io, int32_t n,
                               void* stream);
+
+/* The band height (output rows per workgroup) each frame of a batch of n plans
+ * runs with in pf_fit_planes_batch and the queued batch calls: band_heights[i]
+ * for plans[i] (host array of n entries, written on success).  A plan whose
+ * height was set (pf_plan_derive with band_height > 0, an autotuned height),
+ * whose launch shape has 8-row rounds, or that is not an FP64 full-window
+ * implicit or explicit fit keeps it.  The others start from the default rule
+ * (about one workgroup per resident slot for the frame alone,
+ * pf_plan_band_height); while the batch would hold more workgroups than four per
+ * compute unit of the current device, the plan with the largest window (on
+ * ties the lowest height, then the first such plan) whose height is below 12
+ * rows and below its frame's gets 4 more rows (at most the frame's height).
+ * Host only: no GPU work, nothing enqueued.  PF_ERR_NULL for a NULL pointer,
+ * PF_ERR_SHAPE for n < 0; n = 0 is a no-op. */
+pf_status pf_batch_band_heights(const pf_plan* const* plans, int32_t n, int32_t* band_heights);
 
 /* Bytes of device workspace pf_fit_planes_batch_queued needs for n frames (a
  * 256-byte queue header and one job record per frame); 0 for n <= 0. */

@@ -75,6 +75,7 @@ EXPORTS = ("pf_plan_create", "pf_plan_destroy", "pf_plan_workspace_bytes", "pf_p
            "pf_plan_camera_moments", "pf_fit_planes", "pf_fit_planes_batch",
            "pf_batch_workspace_bytes", "pf_fit_planes_batch_queued",
            "pf_fit_planes_batch_queued_noalloc", "pf_batch_noalloc_max_frames",
+           "pf_batch_band_heights",
            "pf_backward_workspace_bytes", "pf_fit_planes_backward",
            "pf_fit_planes_backward_batch", "pf_fit_planes_xyz",
            "pf_integral_workspace_bytes", "pf_integral_images", "pf_fit_rects",
@@ -117,6 +118,8 @@ def load_library(path: str | None = None):
         lib.pf_fit_planes_batch_queued_noalloc.restype = i32
         lib.pf_batch_noalloc_max_frames.argtypes = []
         lib.pf_batch_noalloc_max_frames.restype = i32
+        lib.pf_batch_band_heights.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i32)]
+        lib.pf_batch_band_heights.restype = i32
         lib.pf_plan_band_height.argtypes = [vp]
         lib.pf_plan_band_height.restype = i32
         lib.pf_plan_autotune.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp,
@@ -280,7 +283,8 @@ def get_plan(intrinsics, height, width, window, mode="implicit", precision="fp64
              shape=None) -> Plan:
     """Cached plan; disparity_scale (1/Z = D * scale) selects disparity input,
     min_valid partial windows, band_height / shape a launch shape other than the
-    built-in one (a derived plan, cached under its own key)."""
+    built-in one (a derived plan, cached under its own key; an explicit band
+    height is never raised by the batch planner, see batch_band_heights)."""
     ds = 0.0 if disparity_scale is None else float(disparity_scale)
     mv = 0 if min_valid is None else int(min_valid)
     key = (tuple(float(v) for v in intrinsics), int(height), int(width), int(window), mode,
@@ -294,7 +298,9 @@ def get_plan(intrinsics, height, width, window, mode="implicit", precision="fp64
             _plan_cache[key] = p
         bh = 0 if band_height is None else int(band_height)
         sh = -1 if shape is None else int(shape)
-        if (bh == 0 or bh == p.tile_h) and (sh == -1 or sh == p.shape):
+        # a band height given explicitly, even the default rule's, is kept by
+        # batch launches (a derived plan); 0 leaves it to the batch planner
+        if bh == 0 and (sh == -1 or sh == p.shape):
             return p
         dkey = key + (bh, sh)
         d = _plan_cache.get(dkey)
@@ -543,23 +549,19 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
     n = len(depths)
     if n == 0:
         return []
-    intr = list(intrinsics) if isinstance(intrinsics[0], (tuple, list)) else [intrinsics] * n
-    ks = list(windows) if isinstance(windows, (tuple, list)) else [windows] * n
     masks = list(valid_masks) if valid_masks is not None else [None] * n
-    mvs = list(min_valid) if isinstance(min_valid, (tuple, list)) else [min_valid] * n
-    bhs = list(band_heights) if isinstance(band_heights, (tuple, list)) else [band_heights] * n
-    if not (len(intr) == len(ks) == len(masks) == len(mvs) == len(bhs) == n):
+    if len(masks) != n:
         raise ValueError("per-frame argument lists must have one entry per frame")
-    dev = depths[0].device
-    plans, ios, results, keep = [], (_FrameIO * n)(), [], []
-    for i, d in enumerate(depths):
+    for d in depths:
         _check_depth(torch, d)
+    plans = _batch_plans([tuple(d.shape) for d in depths], intrinsics, windows, mode, precision,
+                         kappa_flag, disparity_scale, min_valid, band_heights, shape)
+    dev = depths[0].device
+    ios, results, keep = (_FrameIO * n)(), [], []
+    for i, d in enumerate(depths):
         if d.device != dev:
             raise ValueError("all frames must be on one device")
         H, W = d.shape
-        p = get_plan(intr[i], H, W, ks[i], mode, precision, kappa_flag, disparity_scale,
-                     mvs[i], bhs[i], shape)
-        plans.append(p)
         mptr, mpitch = _mask_arg(torch, masks[i], d)
         if outs is None:
             o = (torch.empty((3, H, W), dtype=torch.float32, device=dev),
@@ -594,6 +596,40 @@ def fit_planes_batch(depths, intrinsics, windows, valid_masks=None, *, mode="imp
             code = lib.pf_fit_planes_batch(handles, ios, n, _stream_handle(torch, dev, stream))
     _check(code)
     return results
+
+
+def _batch_plans(shapes, intrinsics, windows, mode, precision, kappa_flag, disparity_scale,
+                 min_valid, band_heights, shape):
+    """The plans of a batch of frames of the given (H, W) shapes."""
+    n = len(shapes)
+    intr = list(intrinsics) if isinstance(intrinsics[0], (tuple, list)) else [intrinsics] * n
+    ks = list(windows) if isinstance(windows, (tuple, list)) else [windows] * n
+    mvs = list(min_valid) if isinstance(min_valid, (tuple, list)) else [min_valid] * n
+    bhs = list(band_heights) if isinstance(band_heights, (tuple, list)) else [band_heights] * n
+    if not (len(intr) == len(ks) == len(mvs) == len(bhs) == n):
+        raise ValueError("per-frame argument lists must have one entry per frame")
+    return [get_plan(intr[i], H, W, ks[i], mode, precision, kappa_flag, disparity_scale,
+                     mvs[i], bhs[i], shape) for i, (H, W) in enumerate(shapes)]
+
+
+def batch_band_heights(shapes, intrinsics, windows, *, mode="implicit", precision="fp64",
+                       kappa_flag=0.0, disparity_scale=None, min_valid=None, band_heights=None,
+                       shape=None):
+    """Band heights (output rows per workgroup) that fit_planes_batch would run
+    each frame of a batch with (pf_batch_band_heights): frames of the given
+    (H, W) shapes (or depth tensors), other arguments as in fit_planes_batch.
+    Fitting a frame alone with band_height set to its entry reproduces its batch
+    outputs bit for bit.  Host only."""
+    shapes = [tuple(x.shape) if hasattr(x, "shape") else tuple(x) for x in shapes]
+    n = len(shapes)
+    if n == 0:
+        return []
+    plans = _batch_plans(shapes, intrinsics, windows, mode, precision, kappa_flag,
+                         disparity_scale, min_valid, band_heights, shape)
+    handles = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    out = (ctypes.c_int32 * n)()
+    _check(load_library().pf_batch_band_heights(handles, n, out))
+    return list(out)
 
 
 def batch_workspace_bytes(n: int) -> int:

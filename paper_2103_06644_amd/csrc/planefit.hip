@@ -324,11 +324,28 @@ __device__ inline df32 disparity(float z, double dscale, df32) {
   return dscale > 0.0 ? df32(z) * to_df32(dscale) : recip(z, df32(0.0f));
 }
 
+// The sample's centred disparity w - w_ref, exactly 0 for an invalid sample.
+// FP64 takes no branch per sample: w = 1/Z (depth input) and w = D * dscale
+// (disparity input) are one blend r m + D s with (m, s) = (1, 0) or
+// (0, dscale), exact either way since a valid sample's reciprocal is finite;
+// an invalid sample's value, whatever it is, is then replaced by 0.
+template <typename T>
+__device__ inline T centred_w(float z, bool ok, T w_ref, double dscale) {
+  if constexpr (std::is_same<T, double>::value) {
+    const double zd = double(z);
+    const double m = dscale > 0.0 ? 0.0 : 1.0, s = dscale > 0.0 ? dscale : 0.0;
+    const double w = fma(rcp_nr(zd), m, zd * s);
+    return ok ? w - w_ref : 0.0;
+  } else {
+    return ok ? disparity(z, dscale, T(0.0f)) - w_ref : T(0.0f);
+  }
+}
+
 template <typename T, bool PARTIAL = false>
 __device__ inline void add_sample(float z, int y, T w_ref, int y_ref, Cursor<T>& c, double dscale) {
   // branch-free: invalid samples contribute exact zeros
   const bool ok = depth_valid(z);
-  const T wh = ok ? disparity(z, dscale, T(0.0f)) - w_ref : T(0.0f);
+  const T wh = centred_w(z, ok, w_ref, dscale);
   c.w += wh;
   c.yw += T(y - y_ref) * wh;
   c.ww += wh * wh;
@@ -345,7 +362,7 @@ __device__ inline void add_sample(float z, int y, T w_ref, int y_ref, Cursor<T>&
 template <typename T, bool PARTIAL = false>
 __device__ inline void sub_sample(float z, int y, T w_ref, int y_ref, Cursor<T>& c, double dscale) {
   const bool ok = depth_valid(z);
-  const T wh = ok ? disparity(z, dscale, T(0.0f)) - w_ref : T(0.0f);
+  const T wh = centred_w(z, ok, w_ref, dscale);
   c.w = c.w - wh;
   c.yw = c.yw - T(y - y_ref) * wh;
   c.ww = c.ww - wh * wh;
@@ -2567,6 +2584,7 @@ struct pf_plan {
   int k, r;
   double S2, N;
   int tile_w, tile_h, n_strips, n_bands;
+  bool band_auto;  // tile_h is the default rule's: a batch launch may raise it
   int shape;  // launch shape (Tiling<shape>)
   // launch shapes other than 0 exist for FP64 implicit / explicit full-window fits
   bool shapes_allowed() const {
@@ -2663,6 +2681,7 @@ pf_status pf_plan_create(const pf_intrinsics* intr, int64_t height, int64_t widt
   const int64_t th = default_band_height(p, p->shape);  // pf_plan_derive sets others
   p->tile_h = int(th);
   p->n_bands = int((height + th - 1) / th);
+  p->band_auto = true;
   *out = p;
   return PF_OK;
 }
@@ -2720,8 +2739,8 @@ pf_status check_batch(const pf_plan* const* plans, const pf_frame_io* io, int32_
   return PF_OK;
 }
 
-// The job of one frame (its workgroups start at wg_begin).
-Job make_job(const pf_plan* p, const pf_frame_io& f, int32_t wg_begin) {
+// The job of one frame (its workgroups start at wg_begin), in bands of tile_h rows.
+Job make_job(const pf_plan* p, const pf_frame_io& f, int32_t wg_begin, int32_t tile_h) {
   auto aligned = [](const void* q, uintptr_t m) { return (reinterpret_cast<uintptr_t>(q) & m) == 0; };
   Job jb;
   std::memset(&jb, 0, sizeof(jb));
@@ -2741,7 +2760,7 @@ Job make_job(const pf_plan* p, const pf_frame_io& f, int32_t wg_begin) {
   jb.W = int32_t(p->W);
   jb.k = p->k;
   jb.tile_w = p->tile_w;
-  jb.tile_h = p->tile_h;
+  jb.tile_h = tile_h;
   jb.n_strips = p->n_strips;
   jb.wg_begin = wg_begin;
   jb.min_valid = int16_t(p->partial() ? p->params.min_valid : 0);
@@ -2751,7 +2770,9 @@ Job make_job(const pf_plan* p, const pf_frame_io& f, int32_t wg_begin) {
   return jb;
 }
 
-int32_t job_groups(const pf_plan* p) { return p->n_strips * p->n_bands; }
+int64_t job_groups(const pf_plan* p, int64_t tile_h) {
+  return int64_t(p->n_strips) * ((p->H + tile_h - 1) / tile_h);
+}
 
 LaunchCommon launch_common(const pf_plan* p) {
   LaunchCommon lc;
@@ -2777,6 +2798,52 @@ int device_cus() {
   if (dev < 64) cache[dev].store(cus, std::memory_order_relaxed);
   return cus;
 }
+
+// Band heights of a batch's frames (tile_h[i] for plans[i]).  The default
+// rule sizes each plan alone, for about one workgroup per resident slot (four
+// per CU), so a batch of such frames has several times the chip's slots in
+// one-round bands: each band repeats its k - 1 warm-up rows for four output
+// rows, and a launch ends on a part-filled round of workgroups.  While the
+// batch holds more workgroups than the chip keeps resident, the largest window
+// (its warm-up is the longest; on ties the lowest band, then the first frame)
+// whose default band height is below 12 rows gets one more round of rows.  Measured on the
+// 640x480 frame at k = 3, 5, 9, 15 (1440 -> 1020 workgroups in 4, 4, 8, 12 rows:
+// 29.4 -> 28.3 us implicit, 19.1 -> 16.9 us explicit) and on the 64-frame mixed
+// batch (12 rows throughout: 336 -> 315 us by value, 398 -> 342 us queued).
+// Only FP64 full-window implicit and explicit plans are raised (the FP32 fit
+// ran 4 % slower so, its kernels keeping more workgroups resident; the
+// compensated one no faster).  Heights set explicitly (pf_plan_derive,
+// autotuned plans) are kept, and so are those of the 8-row-round shape.
+// Planned over the whole batch, so the by-value and the queued launches of one
+// batch run the same bands.
+void batch_band_heights(const pf_plan* const* plans, int32_t n, int32_t* tile_h) {
+  constexpr int32_t kCap = 12;
+  int64_t groups = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    tile_h[i] = plans[i]->tile_h;
+    groups += job_groups(plans[i], tile_h[i]);
+  }
+  const int64_t slots = 4 * int64_t(device_cus());
+  while (groups > slots) {
+    int32_t pick = -1;
+    for (int32_t i = 0; i < n; ++i) {
+      const pf_plan* p = plans[i];
+      if (!p->band_auto || !p->shapes_allowed() || shape_rows(p->shape) != 4 ||
+          tile_h[i] >= kCap || tile_h[i] >= p->H)
+        continue;
+      if (pick < 0 || p->k > plans[pick]->k ||
+          (p->k == plans[pick]->k && tile_h[i] < tile_h[pick]))
+        pick = i;
+    }
+    if (pick < 0) break;
+    groups -= job_groups(plans[pick], tile_h[pick]);
+    // capped at the frame, as pf_plan_derive caps it (the height also places
+    // the band's reference row)
+    tile_h[pick] = int32_t(std::min<int64_t>(tile_h[pick] + 4, plans[pick]->H));
+    groups += job_groups(plans[pick], tile_h[pick]);
+  }
+}
+
 
 // One persistent launch of the instantiation for (T, MODE, MASK, PARTIAL):
 // grid = resident workgroups of the chip (occupancy x compute units), capped
@@ -2827,10 +2894,10 @@ hipError_t launch_queued_modes(const QueueArgs& qa, uint32_t n_items, int mode, 
 // The queued batch after the argument checks: dispatch order (frames with the
 // costliest work items, the largest windows, first, so the queue ends on the
 // cheapest ones; results do not depend on it), job table into `ws` by setup
-// launches, then one persistent fit launch.  `jobs` and `order` are host
-// buffers of n entries.
+// launches, then one persistent fit launch.  `jobs`, `order` and `heights` are
+// host buffers of n entries (heights: per frame, in the caller's order).
 pf_status enqueue_queued(const pf_plan* const* plans, const pf_frame_io* io, int32_t n, void* ws,
-                         void* stream, Job* jobs, int32_t* order) {
+                         void* stream, Job* jobs, int32_t* order, int32_t* heights) {
   // up to kMaxJobs frames fit in one launch's arguments: that launch, whose
   // workgroups the hardware dispatches, is already the single launch the
   // queue would give, without the queue's per-item claim and table reads
@@ -2840,13 +2907,15 @@ pf_status enqueue_queued(const pf_plan* const* plans, const pf_frame_io* io, int
   std::stable_sort(order, order + n,
                    [&](int32_t x, int32_t y) { return plans[x]->k > plans[y]->k; });
   bool has_mask = false;
+  batch_band_heights(plans, n, heights);
   int64_t items = 0;
   for (int32_t j = 0; j < n; ++j) {
     const int32_t i = order[j];
-    if (items + job_groups(plans[i]) > INT32_MAX) return PF_ERR_SHAPE;
-    jobs[j] = make_job(plans[i], io[i], int32_t(items));
+    const int64_t g = job_groups(plans[i], heights[i]);
+    if (items + g > INT32_MAX) return PF_ERR_SHAPE;
+    jobs[j] = make_job(plans[i], io[i], int32_t(items), heights[i]);
     has_mask = has_mask || io[i].mask != nullptr;
-    items += job_groups(plans[i]);
+    items += g;
   }
   QueueHeader* hdr = static_cast<QueueHeader*>(ws);
   Job* table = reinterpret_cast<Job*>(static_cast<char*>(ws) + kQueueHeaderBytes);
@@ -2944,6 +3013,14 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int prec = plans[0]->params.precision;
   const bool expl = plans[0]->params.mode == PF_EXPLICIT;
+  int32_t stack_heights[kMaxJobs];
+  std::vector<int32_t> heap_heights;
+  int32_t* heights = stack_heights;
+  if (n > kMaxJobs) {
+    heap_heights.resize(static_cast<size_t>(n));
+    heights = heap_heights.data();
+  }
+  batch_band_heights(plans, n, heights);
   for (int32_t first = 0; first < n; first += kMaxJobs) {
     const int32_t cnt = std::min<int32_t>(kMaxJobs, n - first);
     LaunchArgs la;
@@ -2955,22 +3032,21 @@ pf_status pf_fit_planes_batch(const pf_plan* const* plans, const pf_frame_io* io
     la.kappa_fp64 = lc.kappa_fp64;
     bool has_mask = false;
     int32_t wg = 0;
-    // dispatch order (implicit solves): the jobs with the longest workgroups
-    // (largest window, whose warm-up is longest) first, so that the launch's
-    // last, partial round of workgroups holds the shortest ones.  Measured +4 %
-    // on a 640x480 frame at k = 3..15 implicit, -2 % explicit (kept in order).
+    // dispatch order: the jobs with the longest workgroups (largest window,
+    // whose warm-up is longest, and the tallest bands) first, so that the
+    // launch's last, partial round of workgroups holds the shortest ones.
     // Results do not depend on the order.
     int32_t order[kMaxJobs];
     for (int32_t j = 0; j < cnt; ++j) order[j] = first + j;
-    if (!expl)
-      std::stable_sort(order, order + cnt,
-                       [&](int32_t x, int32_t y) { return plans[x]->k > plans[y]->k; });
+    std::stable_sort(order, order + cnt,
+                     [&](int32_t x, int32_t y) { return plans[x]->k > plans[y]->k; });
     for (int32_t j = 0; j < cnt; ++j) {
       const pf_plan* p = plans[order[j]];
       const pf_frame_io& f = io[order[j]];
-      la.jobs[j] = make_job(p, f, wg);
+      const int32_t th = heights[order[j]];
+      la.jobs[j] = make_job(p, f, wg, th);
       has_mask = has_mask || f.mask != nullptr;
-      wg += job_groups(p);
+      wg += int32_t(job_groups(p, th));
     }
     la.n_wg = wg;
     const dim3 grid(static_cast<unsigned>(wg));
@@ -3043,8 +3119,8 @@ pf_status pf_fit_planes_batch_queued(const pf_plan* const* plans, const pf_frame
       (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
     return PF_ERR_WORKSPACE;
   std::vector<Job> jobs(static_cast<size_t>(n));
-  std::vector<int32_t> order(static_cast<size_t>(n), 0);
-  return enqueue_queued(plans, io, n, workspace, stream, jobs.data(), order.data());
+  std::vector<int32_t> order(static_cast<size_t>(n), 0), heights(static_cast<size_t>(n), 0);
+  return enqueue_queued(plans, io, n, workspace, stream, jobs.data(), order.data(), heights.data());
 }
 
 pf_status pf_fit_planes_batch_queued_noalloc(const pf_plan* const* plans, const pf_frame_io* io,
@@ -3056,11 +3132,21 @@ pf_status pf_fit_planes_batch_queued_noalloc(const pf_plan* const* plans, const 
   const pf_status st = scratch_for_current_device(&ws);
   if (st != PF_OK) return st;
   Job jobs[kNoAllocJobs];
-  int32_t order[kNoAllocJobs];
-  return enqueue_queued(plans, io, n, ws, stream, jobs, order);
+  int32_t order[kNoAllocJobs], heights[kNoAllocJobs];
+  return enqueue_queued(plans, io, n, ws, stream, jobs, order, heights);
 }
 
 int32_t pf_batch_noalloc_max_frames(void) { return kNoAllocJobs; }
+
+pf_status pf_batch_band_heights(const pf_plan* const* plans, int32_t n, int32_t* band_heights) {
+  if (n < 0) return PF_ERR_SHAPE;
+  if (n == 0) return PF_OK;
+  if (!plans || !band_heights) return PF_ERR_NULL;
+  for (int32_t i = 0; i < n; ++i)
+    if (!plans[i]) return PF_ERR_NULL;
+  batch_band_heights(plans, n, band_heights);
+  return PF_OK;
+}
 
 pf_status pf_fit_planes(const pf_plan* plan, const float* depth, int64_t depth_pitch,
                         const uint8_t* mask, int64_t mask_pitch, float* normals,
@@ -3088,6 +3174,7 @@ pf_status pf_plan_derive(const pf_plan* plan, int32_t band_height, int32_t shape
   const int64_t th = band_height > 0 ? band_height : default_band_height(p, p->shape);
   p->tile_h = int(std::min<int64_t>(th, p->H));
   p->n_bands = int((p->H + p->tile_h - 1) / p->tile_h);
+  p->band_auto = band_height == 0;
   *out = p;
   return PF_OK;
 }
@@ -3105,6 +3192,7 @@ pf_status pf_plan_autotune(const pf_plan* plan, const float* depth, int64_t dept
   if (st != PF_OK) return st;
   // candidates run on a private copy: the caller's plan is never written
   pf_plan trial(*plan);
+  trial.band_auto = false;  // each candidate runs at exactly its own band height
   const pf_plan* tp = &trial;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;

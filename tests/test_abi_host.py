@@ -336,6 +336,60 @@ def test_derive_leaves_the_plan_alone():
         lib.pf_plan_destroy(h)
 
 
+def _groups(H, W, k, th):
+    tw_max = ((256 - (k - 1)) // 4) * 4
+    return -(-W // tw_max) * -(-H // th)
+
+
+def test_batch_band_heights():
+    """The batch planner (pf_batch_band_heights; host only, 256 CUs here and on
+    MI355X): a batch of more workgroups than four per CU gets taller bands,
+    largest windows first (equal windows: lowest band first), one 4-row round at
+    a time up to 12 rows, until it fits; explicit heights and 8-row-round shapes
+    are kept; a frame alone keeps the default rule's height."""
+    intr = (525.0, 525.0, 319.5, 239.5)
+    vga4 = [(480, 640)] * 4
+    for mode in ("implicit", "explicit"):
+        # 640x480 at k = 3, 5, 9, 15: 4 x 360 workgroups -> 1020 <= 1024
+        h = pf.batch_band_heights(vga4, intr, [3, 5, 9, 15], mode=mode)
+        assert h == [4, 4, 8, 12]
+        assert sum(_groups(480, 640, k, t) for k, t in zip([3, 5, 9, 15], h)) <= 1024
+        # the caller's order does not matter, only the windows
+        assert pf.batch_band_heights(vga4, intr, [15, 3, 9, 5], mode=mode) == [12, 4, 8, 4]
+        # ties: the lowest band first, then the first frame
+        assert pf.batch_band_heights(vga4, intr, [9, 9, 9, 9], mode=mode) == [8, 8, 8, 4]
+    # heights given explicitly are kept, even the default rule's own
+    assert pf.batch_band_heights(vga4, intr, [3, 5, 9, 15], band_heights=4) == [4, 4, 4, 4]
+    assert pf.batch_band_heights(vga4, intr, [3, 5, 9, 15],
+                                 band_heights=[None, None, 4, None]) == [4, 8, 4, 12]
+    # the 8 x 8 shape (8-row rounds) keeps its own rule, and so do the FP32,
+    # compensated, partial-window and literal fits
+    assert pf.batch_band_heights(vga4, intr, [3, 5, 9, 15], shape=2) == [8, 8, 8, 8]
+    for kw in (dict(precision="fp32"), dict(precision="compensated"), dict(min_valid=5),
+               dict(mode="implicit_literal")):
+        assert pf.batch_band_heights(vga4, intr, [3, 5, 9, 15], **kw) == [4, 4, 4, 4], kw
+    # alone, or a batch that fits: the default rule
+    assert pf.batch_band_heights([(480, 640)], intr, [15]) == [4]
+    assert pf.batch_band_heights([(480, 640)] * 2, intr, [15, 3]) == [4, 4]
+    assert pf.batch_band_heights([(1080, 1920)], intr, [31]) == [12]
+    # a large batch: every frame at the 12-row cap, still more than the slots
+    sizes = [(240, 320)] * 24 + [(480, 640)] * 32 + [(720, 1280)] * 8
+    ks = [3, 5, 7, 9, 15] * 12 + [3, 5, 7, 9]
+    h = pf.batch_band_heights(sizes, intr, ks)
+    assert h == [12] * 64
+    # a frame shorter than the cap stops at its own height, and the planner
+    # stops once the batch fits (300 x 6 workgroups, 3 fewer per raised frame)
+    h = pf.batch_band_heights([(6, 640)] * 300, intr, [3] * 300)
+    assert h == [6] * 259 + [4] * 41
+    assert sum(_groups(6, 640, 3, t) for t in h) == 1023
+    assert pf.batch_band_heights([], intr, 5) == []
+    lib = pf.load_library()
+    out = (ctypes.c_int32 * 1)()
+    assert lib.pf_batch_band_heights(None, 1, out) == 1
+    assert lib.pf_batch_band_heights(None, -1, out) == 2
+    assert lib.pf_batch_band_heights(None, 0, None) == 0
+
+
 def test_output_tensor_checks():
     """The binding refuses out tensors of the wrong shape, dtype, layout or
     device before any pointer reaches the library (the kernels write the

@@ -1,8 +1,9 @@
 """Batched launches: many frames of mixed sizes and window sizes per kernel launch.
 
 Every frame of a batch must come out bit-identical to the same frame fitted
-alone (each workgroup does the same arithmetic whatever else shares its
-launch), and sampled pixels must match the FP64 oracle.  The batch here is a
+alone at the band height the batch ran it with (each workgroup does the same
+arithmetic whatever else shares its launch; pf_batch_band_heights reports the
+heights), and sampled pixels must match the FP64 oracle.  The batch here is a
 cut-down version of the 64-frame mixed workload (more than 32 frames, so it
 spans two launches)."""
 import numpy as np
@@ -35,9 +36,10 @@ def test_batch_matches_single_and_oracle(gpu, mode):
     ks = [f.window for f in frames]
     outs = pf.fit_planes_batch(depths, intr, ks, mode=mode)
     torch.cuda.synchronize()
+    heights = pf.batch_band_heights(depths, intr, ks, mode=mode)
     rng = np.random.Generator(np.random.PCG64(9))
     for i, f in enumerate(frames):
-        single = pf.fit_planes(depths[i], intr[i], ks[i], mode=mode)
+        single = pf.fit_planes(depths[i], intr[i], ks[i], mode=mode, band_height=heights[i])
         torch.cuda.synchronize()
         for a, b in zip(outs[i], single):
             assert torch.equal(torch.nan_to_num(a.float(), nan=-7.0),

@@ -66,8 +66,10 @@ def test_disparity_batch_and_backward(gpu):
     ds = [torch.from_numpy(_disp(f.depth)).cuda() for f in fr]
     intr = fr[0].intrinsics
     batch = pf.fit_planes_batch(ds, intr, [5, 9, 3], disparity_scale=SCALE)
+    # each frame alone at the band height the batch ran it with
+    heights = pf.batch_band_heights(ds, intr, [5, 9, 3], disparity_scale=SCALE)
     for i, k in enumerate([5, 9, 3]):
-        single = pf.fit_planes(ds[i], intr, k, disparity_scale=SCALE)
+        single = pf.fit_planes(ds[i], intr, k, disparity_scale=SCALE, band_height=heights[i])
         for a, b in zip(batch[i], single):
             assert torch.equal(a, b) or torch.allclose(a, b, equal_nan=True, rtol=0, atol=0)
     # backward: dL/dD against the autograd reference on Z = 1/(D s)

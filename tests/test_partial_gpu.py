@@ -81,8 +81,9 @@ def test_partial_collinear_batch_and_full_rule(gpu):
     fr = frames_for("vga_640x480")[0]
     ds = [torch.from_numpy(fr.depth).cuda(), torch.from_numpy(fr.depth[:200, :300].copy()).cuda()]
     batch = pf.fit_planes_batch(ds, fr.intrinsics, [9, 9], min_valid=40)
+    heights = pf.batch_band_heights(ds, fr.intrinsics, [9, 9], min_valid=40)
     for i in range(2):
-        single = pf.fit_planes(ds[i], fr.intrinsics, 9, min_valid=40)
+        single = pf.fit_planes(ds[i], fr.intrinsics, 9, min_valid=40, band_height=heights[i])
         for x, y in zip(batch[i], single):
             assert torch.equal(torch.nan_to_num(x.float(), 7.0), torch.nan_to_num(y.float(), 7.0))
     # one launch, min_valid per frame (k^2 / 2 at each window size), both solves
@@ -90,8 +91,10 @@ def test_partial_collinear_batch_and_full_rule(gpu):
     mvs = [max(3, k * k // 2) for k in ks]
     for mode in ("implicit", "explicit"):
         batch = pf.fit_planes_batch([ds[0]] * 4, fr.intrinsics, ks, mode=mode, min_valid=mvs)
+        heights = pf.batch_band_heights([ds[0]] * 4, fr.intrinsics, ks, mode=mode, min_valid=mvs)
         for i, (k, mv) in enumerate(zip(ks, mvs)):
-            single = pf.fit_planes(ds[0], fr.intrinsics, k, mode=mode, min_valid=mv)
+            single = pf.fit_planes(ds[0], fr.intrinsics, k, mode=mode, min_valid=mv,
+                                   band_height=heights[i])
             for x, y in zip(batch[i], single):
                 assert torch.equal(torch.nan_to_num(x.float(), 7.0),
                                    torch.nan_to_num(y.float(), 7.0)), (mode, k)

@@ -1540,11 +1540,10 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
           // of all four windows are taken first; then the wave packs its valid
           // windows into consecutive slots of its own LDS rows (only this wave
           // reads them, and it has read them all: LDS serves a wave's accesses
-          // in order), the other in-frame pixels after them, and solves 64
-          // slots at a time.  Results are those of the per-lane solve, bit for
-          // bit.
+          // in order), the other pixels after them, and solves 64 slots at a
+          // time.  Results are those of the per-lane solve, bit for bit.
           T pB[4], pX[4], pY[4], pQ[4];
-          bool keep[4], fit[4];
+          bool fit[4];
           // the run's columns, opaque to the compiler: the LDS addresses of
           // the four steps are then formed here in each round rather than
           // hoisted out of the round loop, where they would hold registers
@@ -1559,18 +1558,15 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
             pQ[q] = hww;
             pX[q] = hx - T(q) * hw;
             pY[q] = hy - T(y0 - y_ref) * hw;
-            keep[q] = o0s + q < cols;
-            fit[q] = keep[q] && hn == a.k * a.k;
+            fit[q] = o0s + q < cols && hn == a.k * a.k;
             leave(o);
           }
-          uint64_t mfit[4], mrest[4];
-          int nfit = 0, nrest = 0;
+          uint64_t mfit[4];
+          int nfit = 0;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             mfit[q] = __builtin_amdgcn_ballot_w64(fit[q]);
-            mrest[q] = __builtin_amdgcn_ballot_w64(keep[q] && !fit[q]);
             nfit += __builtin_popcountll(mfit[q]);
-            nrest += __builtin_popcountll(mrest[q]);
           }
           T* kB = sw + hj * kPitch;
           T* kX = syw + hj * kPitch;
@@ -1579,34 +1575,33 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
           uint8_t* kc = reinterpret_cast<uint8_t*>(kQ + kBlock);
           static_assert(kBlock * sizeof(T) + kBlock <= kNPitch * sizeof(int), "packed row");
           __asm__ volatile("" ::: "memory");  // every read of the column sums comes first
+          // every window of the wave gets a slot: the valid ones 0 .. nfit-1,
+          // the others (a pixel past the strip, the frame or the band among
+          // them, whose column then fails the store's range test) the rest, in
+          // (window of the run, lane) order; a slot's sums are read only below
+          // nfit, so the others are written unconditionally too
+          const int lane = tid & 63;
           int sf = 0, sr = nfit;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const uint64_t mf = mfit[q], mr = mrest[q];
+            const uint64_t mf = mfit[q];
             const int bf = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mf >> 32),
                                                          __builtin_amdgcn_mbcnt_lo(uint32_t(mf), 0u)));
-            const int br = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mr >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo(uint32_t(mr), 0u)));
-            if (fit[q]) {
-              const int s = sf + bf;
-              kB[s] = pB[q];
-              kX[s] = pX[q];
-              kY[s] = pY[q];
-              kQ[s] = pQ[q];
-              kc[s] = uint8_t(o0s + q);
-            } else if (keep[q]) {
-              kc[sr + br] = uint8_t(o0s + q);
-            }
-            sf += __builtin_popcountll(mf);
-            sr += __builtin_popcountll(mr);
+            const int s = fit[q] ? sf + bf : sr + (lane - bf);
+            kB[s] = pB[q];
+            kX[s] = pX[q];
+            kY[s] = pY[q];
+            kQ[s] = pQ[q];
+            kc[s] = uint8_t(o0s + q);
+            const int cf = __builtin_popcountll(mf);
+            sf += cf;
+            sr += 64 - cf;
           }
           __asm__ volatile("" ::: "memory");
-          const int lane = tid & 63;
-          const int n = nfit + nrest;
 #pragma unroll 1
-          for (int s0 = 0; s0 < n; s0 += 64) {
+          for (int s0 = 0; s0 < kBlock; s0 += 64) {
             const int s = s0 + lane;
-            const int c = s < n ? int(kc[s]) : 0;
+            const int c = int(kc[s]);
             PixelOut po = invalid_pixel();
             if (s < nfit) {
               if constexpr (std::is_same<T, df32>::value)
@@ -1614,7 +1609,7 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
               else
                 po = solve_pixel<T, MODE>(a, kB[s], kX[s], kY[s], kQ[s], a.k * a.k, w_ref, ox0 + c, y0);
             }
-            ro.put(s < n ? ro.at(c, cols) : kDropOffset, po);
+            ro.put(ro.at(c, cols), po);
           }
         } else if constexpr (MODE != PF_EXPLICIT) {
           // one pixel at a time, each stored as soon as it is solved (the

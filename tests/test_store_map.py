@@ -14,8 +14,9 @@ a pixel outside the strip, the frame or the band a drop offset instead.
 
 Implicit fits with runs of four pack each wave's windows before solving: the
 windows with a full valid count take slots 0 .. nfit-1 in (window of the run,
-lane) order, the other in-frame pixels the slots after them, each slot keeping
-its column; slot s is then solved and stored by lane s % 64 in round s / 64.
+lane) order, every other window of the wave the slots after them, each slot
+keeping its column; slot s is then solved (below nfit) and stored by lane
+s % 64 in round s / 64, dropped when its column lies past the row's range.
 Which windows are valid depends on the depth, so the emulation draws it at
 random."""
 import numpy as np
@@ -53,31 +54,29 @@ def emulate_packed(hits, W, ox0, tile_w, yg, nr, rng, p_fit):
         cols = min(tile_w, W - ox0) if hj < nr else 0
         keep = 4 * np.arange(64)[None, :] + np.arange(4)[:, None] < cols
         fit = keep & (rng.random((4, 64)) < p_fit)
-        nfit, nrest = int(fit.sum()), int((keep & ~fit).sum())
-        n = nfit + nrest
-        assert n <= BLOCK
+        nfit = int(fit.sum())
         # the packed row: 256 doubles then 256 column bytes inside the count row
         assert BLOCK * 8 + BLOCK <= KPITCH_N * 4
         col = np.full(BLOCK, -1)
         sf, sr = 0, nfit
         lanes = np.arange(64)
         for q in range(4):
-            rest = keep[q] & ~fit[q]
-            # mbcnt: set bits of the wave's ballot below each lane
-            for mask, start in ((fit[q], sf), (rest, sr)):
-                below = np.cumsum(mask) - mask
-                slots = start + below[mask]
-                assert (col[slots] == -1).all()
-                col[slots] = 4 * lanes[mask] + q
-            assert (col[sf:sf + fit[q].sum()] >= 0).all()
-            sf += int(fit[q].sum())
-            sr += int(rest.sum())
-        assert sf == nfit and sr == n
-        assert (col[:n] >= 0).all() and (col[n:] == -1).all()
-        assert (col[:n] < 256).all()                          # kept in one byte
-        # round s // 64, lane s % 64 stores slot s: every slot below n, once
-        c = col[:n]
-        assert (c < cols).all()
+            # mbcnt: valid windows of the wave below each lane; the others
+            # (every window that is not valid, kept or not) take lane - that
+            bf = np.cumsum(fit[q]) - fit[q]
+            slots = np.where(fit[q], sf + bf, sr + (lanes - bf))
+            assert (col[slots] == -1).all()
+            col[slots] = 4 * lanes + q
+            cf = int(fit[q].sum())
+            sf += cf
+            sr += 64 - cf
+        assert sf == nfit and sr == BLOCK and (col >= 0).all()
+        assert (col < 256).all()                              # kept in one byte
+        # the slots below nfit hold exactly the valid windows
+        assert sorted(col[:nfit]) == sorted((4 * lanes[None, :] + np.arange(4)[:, None])[fit])
+        # round s // 64, lane s % 64 stores slot s; a column past the row's
+        # range (past the strip, the frame or the band) is dropped
+        c = col[col < cols]
         np.add.at(hits, (yg + hj) * W + ox0 + c, 1)
 
 

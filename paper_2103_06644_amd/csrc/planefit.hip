@@ -60,28 +60,29 @@ constexpr int kMaxWindow = 63;
 // threads); `groups` is the number of workgroups per CU the register budget
 // is sized for (four: 128 VGPRs; two: 256).
 //   shape 0: 4 x 4, register budget of four workgroups per CU (128 VGPRs;
-//            32 KB of LDS in FP64);
+//            37 KB of LDS in FP64);
 //   shape 1: 4 x 4, budget of two workgroups per CU (256 VGPRs).  The FP64
-//            implicit kernel still fits in 127, so it runs four per CU like
+//            implicit kernel still fits in 128, so it runs four per CU like
 //            shape 0, with the schedule the larger budget allows (the default
-//            for FP64 implicit fits, measured faster);
-//   shape 2: 8 x 8, two workgroups per CU (64 KB of LDS; half the per-run
+//            for FP64 implicit fits);
+//   shape 2: 8 x 8, two workgroups per CU (74 KB of LDS; half the per-run
 //            warm-up and half the barriers per row).
 // Shapes 1 and 2 exist for FP64 implicit and explicit full-window fits (the
 // autotuner's candidates); every other path runs shape 0.
 //
-// LDS layout of one row of window column sums: column i lives at
-// (i % run) * sub + i / run.  In the horizontal phase, where almost all LDS
-// traffic is (two reads per channel per output), the runs of a row read the
-// same (i % run) with consecutive i / run: consecutive words, no bank
-// conflicts.  The vertical phase writes each column once per row with a
-// stride of sub between neighbouring threads, which can cost two-way bank
-// conflicts on those writes.
+// LDS layout of one row of window column sums: column i lives at record
+// (i % run) * sub + i / run, each record 16 bytes (see ColumnSums).  In the
+// horizontal phase, where almost all LDS traffic is (two reads per column
+// per output), the runs of a row read the same (i % run) with consecutive
+// i / run: consecutive records, no bank conflicts.  The vertical phase writes
+// each column once per row, neighbouring threads `sub` records apart; with
+// 16 * sub = 32 (mod 128) bytes the eight lanes a 16-byte LDS access serves
+// per cycle hit eight different 16-byte bank groups.
 template <int SHAPE>
 struct Tiling;
 template <>
 struct Tiling<0> {
-  static constexpr int rows = 4, run = 4, sub = 72, groups = 4;
+  static constexpr int rows = 4, run = 4, sub = 74, groups = 4;
 };
 template <>
 struct Tiling<1> : Tiling<0> {
@@ -89,10 +90,12 @@ struct Tiling<1> : Tiling<0> {
 };
 template <>
 struct Tiling<2> {
-  static constexpr int rows = 8, run = 8, sub = 36, groups = 2;
+  static constexpr int rows = 8, run = 8, sub = 37, groups = 2;
 };
 constexpr int kShapes = 3;
-constexpr int kPitch = 288;  // LDS entries per row, >= kBlock for every tiling
+constexpr int kPitch = 296;  // LDS records per row, >= kBlock for every tiling
+static_assert((16 * Tiling<0>::sub) % 128 == 32, "shape 0 write banks");
+static_assert((16 * Tiling<2>::sub) % 128 == 80, "shape 2 write banks");
 static_assert(Tiling<0>::run * Tiling<0>::sub == kPitch, "pitch");
 static_assert(Tiling<2>::run * Tiling<2>::sub == kPitch, "pitch");
 static_assert(Tiling<0>::rows * kBlock / Tiling<0>::run == kBlock, "split");
@@ -1198,6 +1201,44 @@ __device__ inline int64_t bwd_ws_offset(const LaunchArgs& la, int jb) {
 
 // Workgroups per CU the register budget is sized for: the forward sweeps
 // (32 KB of LDS) are held to 128 VGPRs so that four waves share a SIMD.
+// One column's window sums.  In LDS they are 16-byte records: FP32 keeps the
+// four values in one record, FP64 and two-float keep (w, yw) and (ww, n) in
+// two arrays of records, so that the lanes of a wave read and write
+// consecutive 16-byte words (two LDS instructions per column).
+template <typename T>
+struct ColumnSums {
+  T w, yw, ww;  // sums of w - w_ref, (y - y_ref)(w - w_ref), (w - w_ref)^2
+  int n;        // valid samples
+};
+template <typename T>
+struct alignas(16) Pair16 {
+  T a, b;
+};
+// (ww, n) as one 12-byte access to a 16-byte record: narrower accesses at a
+// 16-byte lane stride would conflict in the LDS banks
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+static_assert(sizeof(u32x3) == 16, "three-word vectors take 16-byte records");
+template <typename T>
+__device__ inline u32x3 pack_ww_n(T ww, int n) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, ww);
+  return u32x3{uint32_t(b), uint32_t(b >> 32), uint32_t(n)};
+}
+template <typename T>
+__device__ inline void unpack_ww_n(u32x3 v, T& ww, int& n) {
+  ww = __builtin_bit_cast(T, uint64_t(v.x) | (uint64_t(v.y) << 32));
+  n = int(v.z);
+}
+template <typename T>
+struct alignas(16) Col16 {
+  T w, yw, ww;
+  int n;
+};
+template <typename T>
+constexpr bool kWideSums = sizeof(T) > 4;
+static_assert(sizeof(Pair16<double>) == 16 && sizeof(Pair16<df32>) == 16, "FP64 records");
+static_assert(sizeof(df32) == 8, "two-float values pack into 64 bits");
+static_assert(sizeof(Col16<float>) == 16, "FP32 record");
+
 template <typename T, int MODE, bool BWD, bool PARTIAL, int SHAPE = 0>
 constexpr int kMinGroups =
     (MODE != PF_IMPLICIT_LITERAL && !BWD && !PARTIAL) ? Tiling<SHAPE>::groups : 1;
@@ -1253,14 +1294,44 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
   a.min_valid = job.min_valid;
 
   // Implicit forward fits with runs of four pack each wave's valid windows
-  // before solving them (below); the count rows are then twice as long, so
-  // that a wave's four rows hold its 256 packed windows.
+  // before solving them (below), over the wave's own row of column sums.
   constexpr bool PACK = MODE != PF_EXPLICIT && !BWD && !PARTIAL && TL::run == 4;
-  constexpr int kNPitch = PACK ? 2 * kPitch : kPitch;
-  __shared__ T sw[TL::rows * kPitch];
-  __shared__ T syw[TL::rows * kPitch];
-  __shared__ T sww[TL::rows * kPitch];
-  __shared__ __align__(16) int sn[TL::rows * kNPitch];
+  constexpr bool WIDE = kWideSums<T>;
+  __shared__ Pair16<T> cs_lo[WIDE ? TL::rows * kPitch : 1];   // (w, yw)
+  __shared__ u32x3 cs_hi[WIDE ? TL::rows * kPitch : 1];       // (ww, n)
+  __shared__ Col16<T> cs_one[WIDE ? 1 : TL::rows * kPitch];   // FP32: all four
+  auto put_col = [&](int idx, const ColumnSums<T>& c) {
+    if constexpr (WIDE) {
+      Pair16<T> lo;
+      lo.a = c.w;
+      lo.b = c.yw;
+      cs_lo[idx] = lo;
+      cs_hi[idx] = pack_ww_n(c.ww, c.n);
+    } else {
+      Col16<T> r;
+      r.w = c.w;
+      r.yw = c.yw;
+      r.ww = c.ww;
+      r.n = c.n;
+      cs_one[idx] = r;
+    }
+  };
+  auto get_col = [&](int idx) -> ColumnSums<T> {
+    ColumnSums<T> c;
+    if constexpr (WIDE) {
+      const Pair16<T> lo = cs_lo[idx];
+      c.w = lo.a;
+      c.yw = lo.b;
+      unpack_ww_n(cs_hi[idx], c.ww, c.n);
+    } else {
+      const Col16<T> r = cs_one[idx];
+      c.w = r.w;
+      c.yw = r.yw;
+      c.ww = r.ww;
+      c.n = r.n;
+    }
+    return c;
+  };
   __shared__ int syn[PARTIAL ? TL::rows * kPitch : 1];   // partial windows: sum y~ per column
   __shared__ int sy2n[PARTIAL ? TL::rows * kPitch : 1];  // and sum y~^2
   __shared__ double red[2 * (kBlock / 64)];
@@ -1375,19 +1446,21 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
         const int y0 = yg + j;
         if (y0 > yb) sub_sample<T, PARTIAL>(zg[j], y0 - a.r - 1, w_ref, y_ref, col, a.dscale);
         add_sample<T, PARTIAL>(zl[j], y0 + a.r, w_ref, y_ref, col, a.dscale);
-        sw[j * kPitch + li] = col.w;
-        syw[j * kPitch + li] = col.yw;
-        sww[j * kPitch + li] = col.ww;
-        sn[j * kNPitch + li] = col.n;
+        ColumnSums<T> c;
+        c.w = col.w;
+        c.yw = col.yw;
+        c.ww = col.ww;
+        c.n = col.n;
+        put_col(j * kPitch + li, c);
         if (PARTIAL) {
           syn[j * kPitch + li] = col.yn;
           sy2n[j * kPitch + li] = col.y2n;
         }
       } else if (!BWD) {
-        sw[j * kPitch + li] = T(0);
-        syw[j * kPitch + li] = T(0);
-        sww[j * kPitch + li] = T(0);
-        sn[j * kNPitch + li] = 0;
+        ColumnSums<T> c;
+        c.w = c.yw = c.ww = T(0);
+        c.n = 0;
+        put_col(j * kPitch + li, c);
         if (PARTIAL) {
           syn[j * kPitch + li] = 0;
           sy2n[j * kPitch + li] = 0;
@@ -1410,10 +1483,7 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
     // stale column sums and stores nothing)
     if (BWD ? (hj < nr && o0 < o1) : true) {
       const int y0 = yg + hj;
-      const T* rw = sw + hj * kPitch;
-      const T* ryw = syw + hj * kPitch;
-      const T* rww = sww + hj * kPitch;
-      const int* rn = sn + hj * kNPitch;
+      const int rc = hj * kPitch;  // first record of this thread's row
       const int base = o0 + a.r;  // x - x_c = (i - base) - (o - o0)
       // window sums slid along the run: column o + k - 1 enters as column o leaves
       T hw = T(0), hx = T(0), hy = T(0), hww = T(0);
@@ -1422,14 +1492,14 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
       int hxn = 0, hx2n = 0, hyn = 0, hxyn = 0, hy2n = 0;
       auto enter = [&](int i) {
         const int l = lds_index<SHAPE>(i);
-        const T v = rw[l];
-        hw += v;
-        hx += T(i - base) * v;
-        hy += ryw[l];
-        hww += rww[l];
-        hn += rn[l];
+        const ColumnSums<T> v = get_col(rc + l);
+        hw += v.w;
+        hx += T(i - base) * v.w;
+        hy += v.yw;
+        hww += v.ww;
+        hn += v.n;
         if (PARTIAL) {
-          const int dx = i - base, n = rn[l], yn = syn[hj * kPitch + l];
+          const int dx = i - base, n = v.n, yn = syn[hj * kPitch + l];
           hxn += dx * n;
           hx2n += dx * dx * n;
           hyn += yn;
@@ -1439,14 +1509,14 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
       };
       auto leave = [&](int i) {
         const int l = lds_index<SHAPE>(i);
-        const T v = rw[l];
-        hw = hw - v;
-        hx = hx - T(i - base) * v;
-        hy = hy - ryw[l];
-        hww = hww - rww[l];
-        hn -= rn[l];
+        const ColumnSums<T> v = get_col(rc + l);
+        hw = hw - v.w;
+        hx = hx - T(i - base) * v.w;
+        hy = hy - v.yw;
+        hww = hww - v.ww;
+        hn -= v.n;
         if (PARTIAL) {
-          const int dx = i - base, n = rn[l], yn = syn[hj * kPitch + l];
+          const int dx = i - base, n = v.n, yn = syn[hj * kPitch + l];
           hxn -= dx * n;
           hx2n -= dx * dx * n;
           hyn -= yn;
@@ -1568,12 +1638,15 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
             mfit[q] = __builtin_amdgcn_ballot_w64(fit[q]);
             nfit += __builtin_popcountll(mfit[q]);
           }
-          T* kB = sw + hj * kPitch;
-          T* kX = syw + hj * kPitch;
-          T* kY = sww + hj * kPitch;
-          T* kQ = reinterpret_cast<T*>(sn + hj * kNPitch);
-          uint8_t* kc = reinterpret_cast<uint8_t*>(kQ + kBlock);
-          static_assert(kBlock * sizeof(T) + kBlock <= kNPitch * sizeof(int), "packed row");
+          // slot s: (B, Q) and (X, Y) as two 16-byte records over the row's
+          // records (FP32: one record); the slots' columns as bytes after slot
+          // kBlock - 1 of the first array
+          Pair16<T>* kA = WIDE ? cs_lo + hj * kPitch
+                               : reinterpret_cast<Pair16<T>*>(cs_one + hj * kPitch);
+          Pair16<T>* kZ = WIDE ? reinterpret_cast<Pair16<T>*>(cs_hi + hj * kPitch) : nullptr;
+          uint8_t* kc = WIDE ? reinterpret_cast<uint8_t*>(cs_lo + hj * kPitch + kBlock)
+                             : reinterpret_cast<uint8_t*>(cs_one + hj * kPitch + kBlock);
+          static_assert((kPitch - kBlock) * 16 >= kBlock, "slot columns");
           __asm__ volatile("" ::: "memory");  // every read of the column sums comes first
           // every window of the wave gets a slot: the valid ones 0 .. nfit-1,
           // the others (a pixel past the strip, the frame or the band among
@@ -1588,10 +1661,22 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
             const int bf = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mf >> 32),
                                                          __builtin_amdgcn_mbcnt_lo(uint32_t(mf), 0u)));
             const int s = fit[q] ? sf + bf : sr + (lane - bf);
-            kB[s] = pB[q];
-            kX[s] = pX[q];
-            kY[s] = pY[q];
-            kQ[s] = pQ[q];
+            if constexpr (WIDE) {
+              Pair16<T> bq, xy;
+              bq.a = pB[q];
+              bq.b = pQ[q];
+              xy.a = pX[q];
+              xy.b = pY[q];
+              kA[s] = bq;
+              kZ[s] = xy;
+            } else {
+              Col16<T> r;  // B, X, Y in the float slots, Q in the last one
+              r.w = pB[q];
+              r.yw = pX[q];
+              r.ww = pY[q];
+              r.n = __float_as_int(float(pQ[q]));
+              reinterpret_cast<Col16<T>*>(kA)[s] = r;
+            }
             kc[s] = uint8_t(o0s + q);
             const int cf = __builtin_popcountll(mf);
             sf += cf;
@@ -1604,10 +1689,24 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
             const int c = int(kc[s]);
             PixelOut po = invalid_pixel();
             if (s < nfit) {
+              T B, X, Y, Q;
+              if constexpr (WIDE) {
+                const Pair16<T> bq = kA[s], xy = kZ[s];
+                B = bq.a;
+                Q = bq.b;
+                X = xy.a;
+                Y = xy.b;
+              } else {
+                const Col16<T> r = reinterpret_cast<const Col16<T>*>(kA)[s];
+                B = r.w;
+                X = r.yw;
+                Y = r.ww;
+                Q = T(__int_as_float(r.n));
+              }
               if constexpr (std::is_same<T, df32>::value)
-                po = solve_pixel_df<MODE>(a, kB[s], kX[s], kY[s], kQ[s], a.k * a.k, w_ref, ox0 + c, y0);
+                po = solve_pixel_df<MODE>(a, B, X, Y, Q, a.k * a.k, w_ref, ox0 + c, y0);
               else
-                po = solve_pixel<T, MODE>(a, kB[s], kX[s], kY[s], kQ[s], a.k * a.k, w_ref, ox0 + c, y0);
+                po = solve_pixel<T, MODE>(a, B, X, Y, Q, a.k * a.k, w_ref, ox0 + c, y0);
             }
             ro.put(ro.at(c, cols), po);
           }

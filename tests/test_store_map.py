@@ -40,12 +40,12 @@ def geometry(H, W, k, mode, shape=None, band_height=None):
     return tile_w, n_strips, tile_h, -(-H // tile_h), p.shape
 
 
-PITCH = 288                                    # LDS row pitch (columns) of the column sums
-SUB = {4: 72, 8: 36}                          # LDS layout (i % RUN) * SUB + i / RUN
+PITCH = 296                                    # LDS row pitch (16-byte records) of the column sums
+SUB = {4: 74, 8: 37}                          # LDS layout (i % RUN) * SUB + i / RUN
 DROP = 0x80000000
 
 
-KPITCH_N = 2 * PITCH                           # count-row pitch (ints) when windows are packed
+RECORD = 16                                    # bytes per LDS record
 
 
 def emulate_packed(hits, W, ox0, tile_w, yg, nr, rng, p_fit):
@@ -55,8 +55,9 @@ def emulate_packed(hits, W, ox0, tile_w, yg, nr, rng, p_fit):
         keep = 4 * np.arange(64)[None, :] + np.arange(4)[:, None] < cols
         fit = keep & (rng.random((4, 64)) < p_fit)
         nfit = int(fit.sum())
-        # the packed row: 256 doubles then 256 column bytes inside the count row
-        assert BLOCK * 8 + BLOCK <= KPITCH_N * 4
+        # the packed row: slot s in record s of the row (two 16-byte records in
+        # FP64), the slots' column bytes in the records after slot 255
+        assert (PITCH - BLOCK) * RECORD >= BLOCK
         col = np.full(BLOCK, -1)
         sf, sr = 0, nfit
         lanes = np.arange(64)
@@ -164,3 +165,14 @@ def test_packed_implicit_writes_each_pixel_once(H, W, k, p_fit):
         hits = emulate(H, W, k, "implicit", W % 4 == 0, shape, bh, p_fit=p_fit, seed=k)
         assert np.all(hits[:H * W] == 1), np.unique(hits[:H * W], return_counts=True)
         assert not hits[H * W:].any()
+
+
+def test_column_record_writes_spread_over_the_banks():
+    """The vertical phase writes column tid's 16-byte record at (tid % RUN) * SUB
+    + tid / RUN: the eight lanes one LDS cycle serves (128 bytes) land on eight
+    different 16-byte bank groups, for both tilings."""
+    for run in (4, 8):
+        for first in range(0, 64, 8):
+            groups = {(((t % run) * SUB[run] + t // run) * RECORD) % 128 // 16
+                      for t in range(first, first + 8)}
+            assert len(groups) == 8, (run, first, groups)

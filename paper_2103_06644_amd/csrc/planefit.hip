@@ -1639,48 +1639,56 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
             nfit += __builtin_popcountll(mfit[q]);
           }
           // slot s: (B, Q) and (X, Y) as two 16-byte records over the row's
-          // records (FP32: one record); the slots' columns as bytes after slot
-          // kBlock - 1 of the first array
+          // records (FP32: one record), at record (s % 4) * kSlotSub + s / 4:
+          // a dense row writes its slots lane by lane (consecutive records)
+          // and reads them 64 at a time (spread over the bank groups as the
+          // vertical phase's writes); the slots' columns as bytes after
+          // the slots' records of the first array
+          constexpr int kSlotSub = 66;
+          static_assert(kSlotSub >= kBlock / 4 && (16 * kSlotSub) % 128 == 32, "slot layout");
+          static_assert((kPitch - 4 * kSlotSub) * 16 >= kBlock, "slot columns");
+          auto slot_rec = [](int s) { return (s & 3) * kSlotSub + (s >> 2); };
           Pair16<T>* kA = WIDE ? cs_lo + hj * kPitch
                                : reinterpret_cast<Pair16<T>*>(cs_one + hj * kPitch);
           Pair16<T>* kZ = WIDE ? reinterpret_cast<Pair16<T>*>(cs_hi + hj * kPitch) : nullptr;
-          uint8_t* kc = WIDE ? reinterpret_cast<uint8_t*>(cs_lo + hj * kPitch + kBlock)
-                             : reinterpret_cast<uint8_t*>(cs_one + hj * kPitch + kBlock);
-          static_assert((kPitch - kBlock) * 16 >= kBlock, "slot columns");
+          uint8_t* kc = reinterpret_cast<uint8_t*>(kA + 4 * kSlotSub);
           __asm__ volatile("" ::: "memory");  // every read of the column sums comes first
           // every window of the wave gets a slot: the valid ones 0 .. nfit-1,
           // the others (a pixel past the strip, the frame or the band among
-          // them, whose column then fails the store's range test) the rest, in
-          // (window of the run, lane) order; a slot's sums are read only below
-          // nfit, so the others are written unconditionally too
+          // them, whose column then fails the store's range test) the rest,
+          // each kind in column order, so that a row's stores go out to
+          // consecutive columns; a slot's sums are read only below nfit, so
+          // the others are written unconditionally too
           const int lane = tid & 63;
-          int sf = 0, sr = nfit;
+          int below = 0;  // valid windows of the lower lanes
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const uint64_t mf = mfit[q];
-            const int bf = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mf >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo(uint32_t(mf), 0u)));
-            const int s = fit[q] ? sf + bf : sr + (lane - bf);
+            below += int(__builtin_amdgcn_mbcnt_hi(uint32_t(mf >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo(uint32_t(mf), 0u)));
+          }
+          int mine = 0;  // this lane's valid windows before window q
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int s = fit[q] ? below + mine : nfit + (4 * lane - below) + (q - mine);
+            mine += fit[q] ? 1 : 0;
             if constexpr (WIDE) {
               Pair16<T> bq, xy;
               bq.a = pB[q];
               bq.b = pQ[q];
               xy.a = pX[q];
               xy.b = pY[q];
-              kA[s] = bq;
-              kZ[s] = xy;
+              kA[slot_rec(s)] = bq;
+              kZ[slot_rec(s)] = xy;
             } else {
               Col16<T> r;  // B, X, Y in the float slots, Q in the last one
               r.w = pB[q];
               r.yw = pX[q];
               r.ww = pY[q];
               r.n = __float_as_int(float(pQ[q]));
-              reinterpret_cast<Col16<T>*>(kA)[s] = r;
+              reinterpret_cast<Col16<T>*>(kA)[slot_rec(s)] = r;
             }
             kc[s] = uint8_t(o0s + q);
-            const int cf = __builtin_popcountll(mf);
-            sf += cf;
-            sr += 64 - cf;
           }
           __asm__ volatile("" ::: "memory");
 #pragma unroll 1
@@ -1691,13 +1699,13 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
             if (s < nfit) {
               T B, X, Y, Q;
               if constexpr (WIDE) {
-                const Pair16<T> bq = kA[s], xy = kZ[s];
+                const Pair16<T> bq = kA[slot_rec(s)], xy = kZ[slot_rec(s)];
                 B = bq.a;
                 Q = bq.b;
                 X = xy.a;
                 Y = xy.b;
               } else {
-                const Col16<T> r = reinterpret_cast<const Col16<T>*>(kA)[s];
+                const Col16<T> r = reinterpret_cast<const Col16<T>*>(kA)[slot_rec(s)];
                 B = r.w;
                 X = r.yw;
                 Y = r.ww;

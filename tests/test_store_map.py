@@ -13,9 +13,9 @@ the frame), which the hardware enforces by dropping the rest; the kernel sends
 a pixel outside the strip, the frame or the band a drop offset instead.
 
 Implicit fits with runs of four pack each wave's windows before solving: the
-windows with a full valid count take slots 0 .. nfit-1 in (window of the run,
-lane) order, every other window of the wave the slots after them, each slot
-keeping its column; slot s is then solved (below nfit) and stored by lane
+windows with a full valid count take slots 0 .. nfit-1 in column order, every
+other window of the wave the slots after them (also in column order), each
+slot keeping its column; slot s is then solved (below nfit) and stored by lane
 s % 64 in round s / 64, dropped when its column lies past the row's range.
 Which windows are valid depends on the depth, so the emulation draws it at
 random."""
@@ -46,6 +46,7 @@ DROP = 0x80000000
 
 
 RECORD = 16                                    # bytes per LDS record
+SLOT_SUB = 66                                  # packed slot s: record (s % 4) * SLOT_SUB + s / 4
 
 
 def emulate_packed(hits, W, ox0, tile_w, yg, nr, rng, p_fit):
@@ -59,22 +60,28 @@ def emulate_packed(hits, W, ox0, tile_w, yg, nr, rng, p_fit):
         # FP64), the slots' column bytes in the records after slot 255
         assert (PITCH - BLOCK) * RECORD >= BLOCK
         col = np.full(BLOCK, -1)
-        sf, sr = 0, nfit
         lanes = np.arange(64)
+        # valid windows of the lower lanes (the sum over the run of each
+        # window's mbcnt), and this lane's valid windows before window q
+        below = np.cumsum(fit.sum(axis=0)) - fit.sum(axis=0)
+        mine = np.zeros(64, int)
         for q in range(4):
-            # mbcnt: valid windows of the wave below each lane; the others
-            # (every window that is not valid, kept or not) take lane - that
-            bf = np.cumsum(fit[q]) - fit[q]
-            slots = np.where(fit[q], sf + bf, sr + (lanes - bf))
+            slots = np.where(fit[q], below + mine, nfit + (4 * lanes - below) + (q - mine))
             assert (col[slots] == -1).all()
             col[slots] = 4 * lanes + q
-            cf = int(fit[q].sum())
-            sf += cf
-            sr += 64 - cf
+            mine += fit[q]
+        sf, sr = nfit, BLOCK
         assert sf == nfit and sr == BLOCK and (col >= 0).all()
         assert (col < 256).all()                              # kept in one byte
-        # the slots below nfit hold exactly the valid windows
+        # the slots below nfit hold exactly the valid windows, each kind in
+        # column order
         assert sorted(col[:nfit]) == sorted((4 * lanes[None, :] + np.arange(4)[:, None])[fit])
+        assert (np.diff(col[:nfit]) > 0).all() and (np.diff(col[nfit:]) > 0).all()
+        # slot s lives in record (s % 4) * SLOT_SUB + s / 4, below the bytes
+        # of the slots' columns
+        rec = (np.arange(BLOCK) % 4) * SLOT_SUB + np.arange(BLOCK) // 4
+        assert len(set(rec)) == BLOCK and rec.max() < 4 * SLOT_SUB
+        assert 4 * SLOT_SUB * RECORD + BLOCK <= PITCH * RECORD
         # round s // 64, lane s % 64 stores slot s; a column past the row's
         # range (past the strip, the frame or the band) is dropped
         c = col[col < cols]
@@ -176,3 +183,17 @@ def test_column_record_writes_spread_over_the_banks():
             groups = {(((t % run) * SUB[run] + t // run) * RECORD) % 128 // 16
                       for t in range(first, first + 8)}
             assert len(groups) == 8, (run, first, groups)
+
+
+def test_packed_slot_records_spread_over_the_banks():
+    """A dense row writes slot 4 * lane + q from lane `lane` (consecutive
+    records for consecutive lanes) and reads slots s0 + lane: both accesses of
+    eight consecutive lanes fall on eight different 16-byte bank groups."""
+    rec = lambda s: (s % 4) * SLOT_SUB + s // 4
+    for first in range(0, 64, 8):
+        for q in range(4):
+            w = {(rec(4 * L + q) * RECORD) % 128 // 16 for L in range(first, first + 8)}
+            assert len(w) == 8
+        for s0 in range(0, 256, 64):
+            r = {(rec(s0 + L) * RECORD) % 128 // 16 for L in range(first, first + 8)}
+            assert len(r) == 8

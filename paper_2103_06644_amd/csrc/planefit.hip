@@ -206,16 +206,13 @@ __device__ inline float load_depth(const FitArgs& a, int x, int y, bool use = tr
   return in ? z : 0.0f;
 }
 
-// Reciprocal of a positive depth: hardware estimate refined by Newton-Raphson
-// iterations r <- r + r (1 - z r) (two for FP64, one for FP32).  Homogeneous
-// under power-of-two scaling of z, like the rest of the path.
+// Reciprocal of a positive depth: hardware estimate refined by one
+// Newton-Raphson step r <- r + r (1 - z r).  Homogeneous under power-of-two
+// scaling of z, like the rest of the path.
 __device__ inline double recip(float zf, double) {
   const double z = double(depth_valid(zf) ? zf : 1.0f);
-  double r = __builtin_amdgcn_rcp(z);
-  double e = fma(-z, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-z, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(z);
+  return fma(r, fma(-z, r, 1.0), r);
 }
 __device__ inline float recip(float zf, float) {
   const float z = depth_valid(zf) ? zf : 1.0f;
@@ -229,25 +226,21 @@ __device__ inline double rcp_raw(double x) { return __builtin_amdgcn_rcp(x); }
 __device__ inline float rcp_raw(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Reciprocal and reciprocal square root of a positive normal number: hardware
-// estimate plus Newton-Raphson refinement (two steps in FP64, one in FP32).
+// estimate plus one Newton-Raphson step.  The FP64 estimates are good to about
+// 5e-8 (measured on gfx950), so one step leaves about 4e-15 relative error:
+// far below what the float outputs carry, and in a depth sample's 1/Z below
+// any depth noise (the same value is added and taken out again).
 __device__ inline double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
 }
 __device__ inline float rcp_nr(float x) {
   const float r = __builtin_amdgcn_rcpf(x);
   return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 __device__ inline double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  // y <- y (3 - x y^2) / 2
-  double h = 0.5 * x;
-  y = y * fma(-h * y, y, 1.5);
-  y = y * fma(-h * y, y, 1.5);
-  return y;
+  const double y = __builtin_amdgcn_rsq(x);
+  return y * fma(-0.5 * x * y, y, 1.5);  // y <- y (3 - x y^2) / 2
 }
 __device__ inline float rsq_nr(float x) {
   const float y = __builtin_amdgcn_rsqf(x);

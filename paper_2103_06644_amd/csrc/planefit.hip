@@ -668,14 +668,15 @@ __device__ inline void finish_implicit(const FitArgs& a, const Implicit3<S>& c, 
 // coordinates.  FP64 has the range for these sums at every supported depth
 // (1e-3 .. 1e3, k <= 63), so there is no power-of-two scaling.
 //
-// Smallest eigenvalue: Halley's iteration on det(C - l I) from the lower bound
-// c0/c1 (convex and decreasing below l1, so the iterates rise monotonically).
+// Smallest eigenvalue: Halley's iteration on det(C - l I), convex and
+// decreasing below l1, so iterates started below l1 rise monotonically.  C is
+// semidefinite, so 0 lies below l1, and the first iterate is the Halley step
+// from 0: c0 c1 / (c1^2 - c0 c2), which is tighter than Newton's c0/c1.
 // Halley's error obeys e' ~ e^3 / gap^2 with gap = l2 - l1 >= -f'(l)/(c2 - 3l),
-// so the loop stops once a step s has s (c2 - 3l) <= 1e-4 (-f'(l)): the
-// remaining error is then below 1e-12 of the gap (measured on the workload
-// frames: at most 1.5e-10 rad from the converged eigenvector, about one Halley
-// iteration fewer than stopping on a negligible step), or on a step below
-// 1e-13 c2.
+// so the loop stops once a step s has s (c2 - 3l) <= 1e-3 (-f'(l)): the
+// remaining error is then below 1e-9 of the gap (measured on the workload
+// frames: at most 1.2e-9 rad from the converged eigenvector, against 6e-8 for
+// the float rounding of the output), or on a step below 1e-13 c2.
 //
 // Eigenvector: the column of adj(C - l1 I) with the largest diagonal entry.
 // adj(C - l I) = sum_k prod_{j != k} (l_j - l) e_k e_k^T is positive
@@ -716,11 +717,12 @@ __device__ inline PixelOut solve_implicit_fp64(const FitArgs& a, const Moments<d
     const double ln = l - 2.0 * f * fp * rcp_raw(den);
     const bool ok = !done && f > 0.0 && fp < 0.0 && den > 0.0 && ln > l;
     const double step = ln - l;
-    done = !ok || step <= tol || step * (c2 - 3.0 * ln) <= -1e-4 * fp;
+    done = !ok || step <= tol || step * (c2 - 3.0 * ln) <= -1e-3 * fp;
     l = ok ? ln : l;
   };
-  const bool start = c0 > 0.0 && c1 > 0.0;
-  double l = start ? c0 * rcp_nr(c1) : 0.0;
+  const double hden = fma(c1, c1, -c0 * c2);  // >= 2 c1^2 / 3 for real roots
+  const bool start = c0 > 0.0 && c1 > 0.0 && hden > 0.0;
+  double l = start ? c0 * c1 * rcp_nr(hden) : 0.0;
   bool done = !start;
   // almost every window takes two steps: straight-line code, then a loop for
   // the rest

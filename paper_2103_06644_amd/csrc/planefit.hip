@@ -705,9 +705,12 @@ __device__ inline PixelOut solve_implicit_fp64(const FitArgs& a, const Moments<d
   const double c2 = c00 + c11 + c22, c1 = m00 + m11 + m22;
   const double c0 = c00 * m00 + c01 * (c02 * c12 - c01 * c22) + c02 * (c01 * c12 - c02 * c11);
   // One Halley step from l; `done` once a guard fails or the stopping rule
-  // holds (then l stays).  The step's reciprocal needs no refinement: an error
-  // of relative size e in a step of size s leaves e s, which the next step
-  // removes.
+  // holds (then l stays).  Below l1 every factor l_i - l is positive, so
+  // f > 0, f' < 0 and 2 f'^2 - f f'' > 0 there and the step rises; from a
+  // point that rounding put past l1 (f < 0, f' < 0) it would fall, so the
+  // rising-step guard alone stops the iteration there.  The step's
+  // reciprocal needs no refinement: an error of relative size e in a step of
+  // size s leaves e s, which the next step removes.
   const double tol = 1e-13 * c2;
   auto halley = [&](double& l, bool& done) {
     const double f = fma(fma(c2 - l, l, -c1), l, c0);
@@ -715,7 +718,7 @@ __device__ inline PixelOut solve_implicit_fp64(const FitArgs& a, const Moments<d
     const double fpp = fma(-6.0, l, 2.0 * c2);
     const double den = fma(2.0 * fp, fp, -f * fpp);
     const double ln = l - 2.0 * f * fp * rcp_raw(den);
-    const bool ok = !done && f > 0.0 && fp < 0.0 && den > 0.0 && ln > l;
+    const bool ok = !done && den > 0.0 && ln > l;
     const double step = ln - l;
     done = !ok || step <= tol || step * (c2 - 3.0 * ln) <= -1e-3 * fp;
     l = ok ? ln : l;
@@ -757,9 +760,12 @@ __device__ inline PixelOut solve_implicit_fp64(const FitArgs& a, const Moments<d
     nn = vx * vx + vy * vy + vz * vz;
     degenerate = true;
   }
-  const double inv = rsq_nr(nn);
+  // one inverse square root gives both 1/|v| and 1/Sww (the uncentred sum of
+  // w^2, positive in every valid window): r = 1 / (|v| Sww)
+  const double r = rsq_nr(nn * (m.Sww * m.Sww));
+  const double inv = r * m.Sww;
   double n0 = vx * inv, n1 = vy * inv, n2 = vz * inv;
-  const double iS = rcp_nr(m.Sww);
+  const double iS = (r * r) * (nn * m.Sww);
   double d = -fma(n0 * ifx, m.Sxw, fma(n1 * ify, m.Syw, fma(n0, uc, fma(n1, vc, n2)) * m.Sw)) * iS;
   if (facing_flip(d, n0, n1, n2)) {
     d = -d; n0 = -n0; n1 = -n1; n2 = -n2;

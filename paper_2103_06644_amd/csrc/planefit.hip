@@ -1697,8 +1697,14 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
             kc[s] = uint8_t(o0s + q);
           }
           __asm__ volatile("" ::: "memory");
+          // the loop's later trips run at a raised issue priority: a wave
+          // that still has windows to solve there holds up its workgroup at
+          // the round's last barrier, so it issues ahead of waves that are in
+          // earlier phases of their rounds (a wave with no windows left only
+          // issues its stores there)
 #pragma unroll 1
           for (int s0 = 0; s0 < kBlock; s0 += 64) {
+            if (s0 == 64) __builtin_amdgcn_s_setprio(1);
             const int s = s0 + lane;
             const int c = int(kc[s]);
             PixelOut po = invalid_pixel();
@@ -1724,6 +1730,7 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
             }
             ro.put(ro.at(c, cols), po);
           }
+          __builtin_amdgcn_s_setprio(0);
         } else if constexpr (MODE != PF_EXPLICIT) {
           // one pixel at a time, each stored as soon as it is solved (the
           // eigen-solve is large: the loop stays rolled)

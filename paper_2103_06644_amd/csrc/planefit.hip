@@ -1620,22 +1620,45 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
           // time.  Results are those of the per-lane solve, bit for bit.
           T pB[4], pX[4], pY[4], pQ[4];
           bool fit[4];
-          // the run's columns, opaque to the compiler: the LDS addresses of
-          // the four steps are then formed here in each round rather than
-          // hoisted out of the round loop, where they would hold registers
-          // across the solve
-          int ob = o0;
-          __asm__ volatile("" : "+v"(ob));
+          // o0 is a multiple of the run, so column o0 + j sits at record
+          // (j % 4) sub + o0 / 4 + j / 4 of the row: the four leaving columns
+          // (j = q) at fixed offsets from one per-lane record, the entering
+          // ones (j = q + k - 1) at offsets that are the same for every lane,
+          // and their x - base (q - r and q + r) too.  The run's first record
+          // and the window radius are opaque to the compiler: the LDS
+          // addresses and x offsets are then formed here in each round rather
+          // than hoisted out of the round loop, where they would hold
+          // registers across the solve.
+          int rb = rc + o0 / TL::run;
+          __asm__ volatile("" : "+v"(rb));
+          int kr = a.r;
+          __asm__ volatile("" : "+s"(kr));
+          auto enter_rec = [&](int l, int dx) {
+            const ColumnSums<T> v = get_col(l);
+            hw += v.w;
+            hx += T(dx) * v.w;
+            hy += v.yw;
+            hww += v.ww;
+            hn += v.n;
+          };
+          auto leave_rec = [&](int l, int dx) {
+            const ColumnSums<T> v = get_col(l);
+            hw = hw - v.w;
+            hx = hx - T(dx) * v.w;
+            hy = hy - v.yw;
+            hww = hww - v.ww;
+            hn -= v.n;
+          };
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int o = ob + q;
-            enter(o + a.k - 1);
+            const unsigned e = unsigned(q + 2 * kr);  // entering column - o0
+            enter_rec(rb + int((e % 4u) * TL::sub + e / 4u), q + kr);
             pB[q] = hw;
             pQ[q] = hww;
             pX[q] = hx - T(q) * hw;
             pY[q] = hy - T(y0 - y_ref) * hw;
             fit[q] = o0s + q < cols && hn == a.k * a.k;
-            leave(o);
+            leave_rec(rb + q * TL::sub, q - kr);
           }
           uint64_t mfit[4];
           int nfit = 0;

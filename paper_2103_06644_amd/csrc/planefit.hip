@@ -1301,7 +1301,8 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
 
   // Implicit forward fits with runs of four pack each wave's valid windows
   // before solving them (below), over the wave's own row of column sums.
-  constexpr bool PACK = MODE != PF_EXPLICIT && !BWD && !PARTIAL && TL::run == 4;
+  constexpr bool PACK =
+      !PARTIAL && TL::run == 4 && (BWD ? MODE == PF_IMPLICIT : MODE != PF_EXPLICIT);
   constexpr bool WIDE = kWideSums<T>;
   __shared__ Pair16<T> cs_lo[WIDE ? TL::rows * kPitch : 1];   // (w, yw)
   __shared__ u32x3 cs_hi[WIDE ? TL::rows * kPitch : 1];       // (ww, n)
@@ -1436,7 +1437,7 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
   // Forward launches run the horizontal phase on every lane: a lane whose run
   // lies past the strip computes the strip's last run again, and its stores
   // land outside the row's buffer range, which the hardware drops.
-  const int o0 = BWD ? o0s : min(o0s, (a.tile_w - 1) / TL::run * TL::run);
+  const int o0 = (BWD && !PACK) ? o0s : min(o0s, (a.tile_w - 1) / TL::run * TL::run);
   const int o1 = min(o0 + TL::run, a.tile_w);
   const bool vec_store = __builtin_amdgcn_readfirstlane(a.vec_store) != 0;  // uniform per job
 
@@ -1462,7 +1463,7 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
           syn[j * kPitch + li] = col.yn;
           sy2n[j * kPitch + li] = col.y2n;
         }
-      } else if (!BWD) {
+      } else if (!BWD || PACK) {
         ColumnSums<T> c;
         c.w = c.yw = c.ww = T(0);
         c.n = 0;
@@ -1487,7 +1488,7 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
     // horizontal phase: a run of TL::run outputs along one row (forward
     // launches: every lane of every row, see above; a row past the band reads
     // stale column sums and stores nothing)
-    if (BWD ? (hj < nr && o0 < o1) : true) {
+    if ((BWD && !PACK) ? (hj < nr && o0 < o1) : true) {
       const int y0 = yg + hj;
       const int rc = hj * kPitch;  // first record of this thread's row
       const int base = o0 + a.r;  // x - x_c = (i - base) - (o - o0)
@@ -1561,7 +1562,7 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
         leave(o);
         return po;
       };
-      if constexpr (BWD) {
+      if constexpr (BWD && !PACK) {
         // backward: per-window moment gradients from the upstream output gradients
         const int64_t prow = (int64_t)y0 * a.W + ox0;
 #pragma unroll 1
@@ -1601,9 +1602,9 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
           a.gws[3 * a.plane + pp] = mg.Sww;
         }
       } else {
-        // Stores through per-row buffer ranges: a pixel past the strip, the
-        // frame or the band falls outside the range and the hardware drops its
-        // store, so no branch guards a store.  The vector memory counter
+        // Forward: stores through per-row buffer ranges: a pixel past the
+        // strip, the frame or the band falls outside the range and the
+        // hardware drops its store, so no branch guards a store.  The vector memory counter
         // retires in issue order, so the wait for the next round's depth loads
         // (issued before this phase) then counts these stores as issued
         // later and does not wait for them to complete.
@@ -1617,7 +1618,8 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
           // windows into consecutive slots of its own LDS rows (only this wave
           // reads them, and it has read them all: LDS serves a wave's accesses
           // in order), the other pixels after them, and solves 64 slots at a
-          // time.  Results are those of the per-lane solve, bit for bit.
+          // time.  Results are those of the per-lane solve, bit for bit.  The
+          // backward sweep packs the same way and runs the adjoint per slot.
           T pB[4], pX[4], pY[4], pQ[4];
           bool fit[4];
           // o0 is a multiple of the run, so column o0 + j sits at record
@@ -1730,28 +1732,60 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
             if (s0 == 64) __builtin_amdgcn_s_setprio(1);
             const int s = s0 + lane;
             const int c = int(kc[s]);
-            PixelOut po = invalid_pixel();
-            if (s < nfit) {
-              T B, X, Y, Q;
-              if constexpr (WIDE) {
-                const Pair16<T> bq = kA[slot_rec(s)], xy = kZ[slot_rec(s)];
-                B = bq.a;
-                Q = bq.b;
-                X = xy.a;
-                Y = xy.b;
-              } else {
-                const Col16<T> r = reinterpret_cast<const Col16<T>*>(kA)[slot_rec(s)];
-                B = r.w;
-                X = r.yw;
-                Y = r.ww;
-                Q = T(__int_as_float(r.n));
+            if constexpr (BWD) {
+              // moment gradients of the window at column c: zero for an
+              // invalid window, nothing past the strip, the frame or the band
+              if (c < cols) {
+                const int64_t pp = int64_t(y0) * a.W + ox0 + c;
+                MomentGrad mg = {0.0, 0.0, 0.0, 0.0};
+                if (s < nfit) {
+                  const Pair16<T> bq = kA[slot_rec(s)], xy = kZ[slot_rec(s)];
+                  const double B = bq.a, Q = bq.b;
+                  const double uc = (double(ox0 + c) - a.cx) * a.inv_fx;
+                  const double vc = (double(y0) - a.cy) * a.inv_fy;
+                  const double gnx = a.normals ? a.normals[pp] : 0.0;
+                  const double gny = a.normals ? a.normals[a.plane + pp] : 0.0;
+                  const double gnz = a.normals ? a.normals[2 * a.plane + pp] : 0.0;
+                  const double gd = a.offsets ? a.offsets[pp] : 0.0;
+                  const double gr = a.residuals ? a.residuals[pp] : 0.0;
+                  Moments<double> m;
+                  m.Sxw = xy.a;
+                  m.Syw = xy.b;
+                  m.V = a.N * Q - B * B;
+                  m.Sw = a.N * double(w_ref) + B;
+                  m.Sww = Q + double(w_ref) * (2.0 * B + a.N * double(w_ref));
+                  m.SSR = 0.0;
+                  mg = implicit_adjoint(a, m, uc, vc, gnx, gny, gnz, gd, gr);
+                }
+                a.gws[pp] = mg.Sw;
+                a.gws[a.plane + pp] = mg.Sx;
+                a.gws[2 * a.plane + pp] = mg.Sy;
+                a.gws[3 * a.plane + pp] = mg.Sww;
               }
-              if constexpr (std::is_same<T, df32>::value)
-                po = solve_pixel_df<MODE>(a, B, X, Y, Q, a.k * a.k, w_ref, ox0 + c, y0);
-              else
-                po = solve_pixel<T, MODE>(a, B, X, Y, Q, a.k * a.k, w_ref, ox0 + c, y0);
+            } else {
+              PixelOut po = invalid_pixel();
+              if (s < nfit) {
+                T B, X, Y, Q;
+                if constexpr (WIDE) {
+                  const Pair16<T> bq = kA[slot_rec(s)], xy = kZ[slot_rec(s)];
+                  B = bq.a;
+                  Q = bq.b;
+                  X = xy.a;
+                  Y = xy.b;
+                } else {
+                  const Col16<T> r = reinterpret_cast<const Col16<T>*>(kA)[slot_rec(s)];
+                  B = r.w;
+                  X = r.yw;
+                  Y = r.ww;
+                  Q = T(__int_as_float(r.n));
+                }
+                if constexpr (std::is_same<T, df32>::value)
+                  po = solve_pixel_df<MODE>(a, B, X, Y, Q, a.k * a.k, w_ref, ox0 + c, y0);
+                else
+                  po = solve_pixel<T, MODE>(a, B, X, Y, Q, a.k * a.k, w_ref, ox0 + c, y0);
+              }
+              ro.put(ro.at(c, cols), po);
             }
-            ro.put(ro.at(c, cols), po);
           }
           __builtin_amdgcn_s_setprio(0);
         } else if constexpr (MODE != PF_EXPLICIT) {

@@ -1995,14 +1995,18 @@ __global__ __launch_bounds__(kBlock) void grad_depth_fused(LaunchArgs la) {
   struct C5 {
     double a, e, gx, gy, ygy;
   };
+  // branch-free: a sample outside the frame or the strip's columns reads the
+  // workspace's first element and is replaced by zero, so the loads of a
+  // round all issue before the first is waited for
   auto load = [&](int y, C5& c) {
-    c.a = c.e = c.gx = c.gy = c.ygy = 0.0;
-    if (!col_used || y < 0 || y >= H) return;
-    const int64_t p = int64_t(y) * W + x;
-    c.a = gws[p];
-    c.gx = gws[plane + p];
-    c.gy = gws[2 * plane + p];
-    c.e = gws[3 * plane + p];
+    const bool ok = col_used && y >= 0 && y < H;
+    const int64_t p = ok ? int64_t(y) * W + x : 0;
+    const double va = gws[p], vgx = gws[plane + p], vgy = gws[2 * plane + p];
+    const double ve = gws[3 * plane + p];
+    c.a = ok ? va : 0.0;
+    c.gx = ok ? vgx : 0.0;
+    c.gy = ok ? vgy : 0.0;
+    c.e = ok ? ve : 0.0;
     c.ygy = double(y - y_ref) * c.gy;
   };
   C5 lead = {0, 0, 0, 0, 0}, lag = {0, 0, 0, 0, 0};
@@ -2019,16 +2023,21 @@ __global__ __launch_bounds__(kBlock) void grad_depth_fused(LaunchArgs la) {
   const int o0 = run * TL::run, o1 = min(o0 + TL::run, job.tile_w);
   for (int yg = yb; yg < ye; yg += TL::rows) {
     const int nr = min(TL::rows, ye - yg);
+    // every load of the round is issued before any is used: one memory latency
+    // per round instead of one per row and cursor
+    C5 cin[TL::rows], cout[TL::rows];
+#pragma unroll
+    for (int j = 0; j < TL::rows; ++j) {
+      const int y0 = yg + j;
+      load(j < nr ? y0 + r : -1, cin[j]);
+      load(j < nr && y0 > yb ? y0 - r - 1 : -1, cout[j]);
+    }
+#pragma unroll
     for (int j = 0; j < TL::rows; ++j) {
       if (j < nr) {
         const int y0 = yg + j;
-        C5 c;
-        load(y0 + r, c);
-        add(lead, c);
-        if (y0 > yb) {
-          load(y0 - r - 1, c);
-          add(lag, c);
-        }
+        add(lead, cin[j]);
+        if (y0 > yb) add(lag, cout[j]);
         s_a[j * kPitch + li] = lead.a - lag.a;
         s_e[j * kPitch + li] = lead.e - lag.e;
         s_gx[j * kPitch + li] = lead.gx - lag.gx;
@@ -2045,6 +2054,17 @@ __global__ __launch_bounds__(kBlock) void grad_depth_fused(LaunchArgs la) {
       const double* rgy = s_gy + hj * kPitch;
       const double* rygy = s_ygy + hj * kPitch;
       const int base = o0 + r;
+      // the run's depth samples, loaded before the window sums are formed
+      float zq[TL::run];
+#pragma unroll
+      for (int q = 0; q < TL::run; ++q) {
+        const int xi = ox0 + o0 + q;
+        const bool in = o0 + q < o1 && xi < W;
+        const int xs = in ? xi : 0;  // the row's first sample stands in
+        const float z = job.depth[int64_t(y0) * job.depth_pitch + xs];
+        zq[q] = in ? z : 0.0f;
+        if (MASK && job.mask && job.mask[int64_t(y0) * job.mask_pitch + xs] == 0) zq[q] = 0.0f;
+      }
       double h[6] = {0, 0, 0, 0, 0, 0}, g[6] = {0, 0, 0, 0, 0, 0};  // a, e, gx, xgx, gy, ygy
       auto acc = [&](double* s6, int i) {
         const int l = lds_index<0>(i);
@@ -2057,7 +2077,9 @@ __global__ __launch_bounds__(kBlock) void grad_depth_fused(LaunchArgs la) {
         s6[5] += rygy[l];
       };
       for (int i = o0; i < o0 + k - 1; ++i) acc(h, i);
-      for (int q = 0; q < o1 - o0; ++q) {
+#pragma unroll
+      for (int q = 0; q < TL::run; ++q) {
+        if (q >= o1 - o0) break;
         const int o = o0 + q;
         acc(h, o + k - 1);
         const double A = h[0] - g[0], E = h[1] - g[1];
@@ -2066,8 +2088,7 @@ __global__ __launch_bounds__(kBlock) void grad_depth_fused(LaunchArgs la) {
         acc(g, o);
         const int xi = ox0 + o;
         if (xi < W) {
-          float z = job.depth[int64_t(y0) * job.depth_pitch + xi];
-          if (MASK && job.mask && job.mask[int64_t(y0) * job.mask_pitch + xi] == 0) z = 0.0f;
+          const float z = zq[q];
           double dz = 0.0;
           if (depth_valid(z)) {
             // dL/dw, then chained to the input: dw/dZ = -w^2, or dw/dD = dscale

@@ -1245,9 +1245,14 @@ static_assert(sizeof(Pair16<double>) == 16 && sizeof(Pair16<df32>) == 16, "FP64 
 static_assert(sizeof(df32) == 8, "two-float values pack into 64 bits");
 static_assert(sizeof(Col16<float>) == 16, "FP32 record");
 
+// workgroups per CU each kernel is compiled for; the implicit adjoint sweep
+// runs four per CU (as its LDS allows) with a few spilled registers, which is
+// faster than three without
 template <typename T, int MODE, bool BWD, bool PARTIAL, int SHAPE = 0>
 constexpr int kMinGroups =
-    (MODE != PF_IMPLICIT_LITERAL && !BWD && !PARTIAL) ? Tiling<SHAPE>::groups : 1;
+    (MODE != PF_IMPLICIT_LITERAL && !PARTIAL && (!BWD || MODE == PF_IMPLICIT))
+        ? Tiling<SHAPE>::groups
+        : 1;
 
 // Launch-wide parameters of a fit (shared by every frame of a launch).
 struct LaunchCommon {

@@ -1378,6 +1378,10 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
       }
     }
   };
+  // explicit fits spend a larger share of each band in this prologue (their
+  // solve is short): it issues at a raised priority, so its loads go out
+  // ahead of the other workgroups' work
+  if constexpr (MODE == PF_EXPLICIT) __builtin_amdgcn_s_setprio(2);
   const float zref = load_depth<MASK>(a, x, min(y_ref, a.H - 1), col_used);
   issue_warm(0);
   // depth samples of the current round, loaded one round ahead
@@ -1431,6 +1435,7 @@ __device__ __forceinline__ void fit_tile(const Job& job, int wg, const LaunchCom
       if (c < nwarm) add_sample<T, PARTIAL>(zw[j], yb - a.r + c, w_ref, y_ref, col, a.dscale);
     }
   }
+  if constexpr (MODE == PF_EXPLICIT) __builtin_amdgcn_s_setprio(0);
 
   const int li = lds_index<SHAPE>(tid);
   // row of the round this thread fits in the horizontal phase (runs of four:

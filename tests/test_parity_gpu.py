@@ -111,10 +111,13 @@ def test_fp32_path_validity_and_error_report(gpu, mode):
 @pytest.mark.parametrize("mode", ["implicit", "explicit"])
 def test_depth_scaling_bitwise(gpu, mode):
     """Every operation is homogeneous in w = 1/Z: scaling depth by 2^j leaves normals and
-    residuals bit-identical and scales offsets by exactly 2^j."""
+    residuals bit-identical and scales offsets by exactly 2^j.  The extreme scales put the
+    0.5-6 m frame at 2-23 mm and at 64-768 m, near both ends of the supported depth range
+    (1e-3 .. 1e3), so no intermediate of the FP64 sums or solves over- or underflows there."""
     f = frame("vga_640x480")
     base = PT.gpu_fit(f.depth, f.intrinsics, 9, mode)
-    for j in (-3, 4):
+    for j in (-8, -3, 4, 7):
+        _say("depth scale", mode, j)
         s = np.float32(2.0 ** j)
         g = PT.gpu_fit(f.depth * s, f.intrinsics, 9, mode)
         v = (base["status"] & 1) == 0
